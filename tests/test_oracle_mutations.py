@@ -1,0 +1,155 @@
+"""Planted mistakes in the oracle (CPU only) must fail at least one pin.
+
+Each case swaps one oracle function for a plausibly wrong variant, re-runs
+the relevant pin test bodies and expects an assertion to fire.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lps_oracle as O
+import tests.test_oracle_pins as pins
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def _literal_degenerate_slopes(x, y):
+    # the printed degenerate fill (m_{i+1} + m_i) / 2 instead of reading R2
+    n = len(x)
+    m = [(y[i + 1] - y[i]) / (x[i + 1] - x[i]) for i in range(n - 1)]
+    w = [abs(m[i + 1] - m[i]) for i in range(n - 2)]
+    s = [0.0] * n
+    s[0] = (3 * m[0] - m[1]) / 2
+    s[n - 1] = (3 * m[n - 2] - m[n - 3]) / 2
+
+    def wt(i, wr, ml, wl, mr):
+        if wr + wl == 0.0:
+            return (m[i] + m[min(i + 1, n - 2)]) / 2
+        return (wr * ml + wl * mr) / (wr + wl)
+
+    s[1] = wt(1, w[1], m[0], w[0], m[1])
+    s[n - 2] = wt(n - 2, w[n - 3], m[n - 3], w[n - 4], m[n - 2])
+    for i in range(2, n - 2):
+        s[i] = wt(i, w[i], m[i - 1], w[i - 2], m[i])
+    return m, s
+
+
+def _literal_boundary_slopes(x, y):
+    # the printed right-boundary slope (indices shifted) instead of reading R3:
+    # s_{n-2} = (w_{n-4} m_{n-3} + w_{n-3} m_{n-4}) / (w_{n-4} + w_{n-3}), 0-based
+    m, s = _ORIG_SLOPES(x, y)
+    n = len(x)
+    w = [abs(m[i + 1] - m[i]) for i in range(n - 2)]
+    den = w[n - 4] + w[n - 3]
+    if den != 0.0:
+        s[n - 2] = (w[n - 4] * m[n - 3] + w[n - 3] * m[n - 4]) / den
+    return m, s
+
+
+_ORIG_SLOPES = O.akima_slopes
+
+
+def test_mutation_degenerate_weight(monkeypatch):
+    monkeypatch.setattr(O, "akima_slopes", _literal_degenerate_slopes)
+    assert _fails(pins.test_degenerate_weight_reading)
+
+
+def test_mutation_boundary_slope(monkeypatch):
+    monkeypatch.setattr(O, "akima_slopes", _literal_boundary_slopes)
+    assert _fails(pins.test_akima_equals_scipy, 7)
+
+
+def test_mutation_tdi_prefactor(monkeypatch):
+    orig = O.noise_tdi
+
+    def wrong(f, L, A_oms, A_tm):
+        oms, tm = orig(f, L, A_oms, A_tm)
+        xi = 2 * math.pi * f * L / O.C_LIGHT
+        r = np.sin(xi) ** 4 / np.sin(2 * xi) ** 2       # sin^4 read literally
+        return oms * r, tm * r
+
+    monkeypatch.setattr(O, "noise_tdi", wrong)
+    assert _fails(pins.test_noise_tdi_matches_brute_force_x2)
+
+
+def test_mutation_tm_bracket(monkeypatch):
+    orig = O.noise_tdi
+
+    def wrong(f, L, A_oms, A_tm):
+        oms, tm = orig(f, L, A_oms, A_tm)
+        xi = 2 * math.pi * f * L / O.C_LIGHT
+        cx = np.cos(xi)
+        tm = tm.copy()
+        tm[:2] *= (1 + cx) / (1 + cx + cx ** 2)          # dropped cos^2 term
+        return oms, tm
+
+    monkeypatch.setattr(O, "noise_tdi", wrong)
+    assert _fails(pins.test_noise_tdi_matches_brute_force_x2)
+
+
+def test_mutation_dropped_segment_weight(monkeypatch):
+    orig = O.loglike
+
+    def wrong(ds, D, params, knots, k_max=64):
+        if O.state_status(ds, params, knots, k_max):
+            return -math.inf
+        S, _, _ = O.psd(ds, params, knots)
+        return -math.fsum((D / S + np.log(S)).ravel())   # N_k dropped
+
+    monkeypatch.setattr(O, "loglike", wrong)
+    assert _fails(pins.test_loglike_matches_gamma_logpdf, "split")
+
+
+def test_mutation_inverted_ratio(monkeypatch):
+    def wrong(ds, D, params, knots, k_max=64):
+        S, _, _ = O.psd(ds, params, knots)
+        return -math.fsum((ds.nk[None, :] * (S / D + np.log(S))).ravel())   # S/D for D/S
+
+    monkeypatch.setattr(O, "loglike", wrong)
+    assert _fails(pins.test_loglike_matches_gamma_logpdf, "split")
+
+
+def test_mutation_gradient_sign(monkeypatch):
+    orig = O.loglike_grad
+
+    def wrong(ds, D, params, knots, k_max=64):
+        logL, dp, dy, dx = orig(ds, D, params, knots, k_max)
+        return logL, dp, dy, [-v for v in dx]               # wrong sign of dt/dx_i
+
+    monkeypatch.setattr(O, "loglike_grad", wrong)
+    assert _fails(pins.test_gradient_matches_finite_differences, "split")
+
+
+def test_mutation_alpha_pivot(monkeypatch):
+    orig = O.sgwb_tdi
+
+    def wrong(f, R, u, alpha, f_knee):
+        return orig(f, R, u, alpha, 1.0)                    # pivot frequency ignored
+
+    monkeypatch.setattr(O, "sgwb_tdi", wrong)
+    assert _fails(pins.test_sgwb_template_scalings)
+
+
+def test_mutation_route_transposed(monkeypatch):
+    orig = O.perturbed_terms
+
+    def wrong(ds, params, knots):
+        terms = O.template_terms(ds, params)
+        P = O.spline_values(ds, knots)
+        out = terms.copy()
+        for tau in range(4):
+            for c in range(3):
+                j = ds.route[tau][c]
+                if j >= 0:
+                    out[tau, c] = terms[tau, c] * 10.0 ** P[(j + 1) % len(P)]   # wrong spline
+        return out
+
+    monkeypatch.setattr(O, "perturbed_terms", wrong)
+    assert _fails(pins.test_gradient_matches_finite_differences, "split")
