@@ -1,0 +1,195 @@
+/*
+ * lps.h -- C ABI of the batched flexible-PSD / Whittle log-likelihood library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for a batch of MCMC states theta (every walker,
+ * temperature and reversible-jump branch at once), the model of the paper
+ * "A flexible, GPU-accelerated approach for the joint characterization of
+ * LISA instrumental noise and Stochastic Gravitational Wave Backgrounds":
+ *
+ *   S_c(f_k) = sum_tau  T_tau,c(f_k) * amp_tau(theta) * 10^{P_{r(tau,c)}(log10 f_k)}
+ *   logL     = - sum_{c in A,E,T} sum_k  N_k ( D_ck / S_ck + ln S_ck )
+ *
+ *  - T_OMS,c and T_TM,c: the A/E/T noise transfer of Eq. (noise_tdi) applied
+ *    to the OMS and test-mass PSDs of Sec. "Parametrized noise model"
+ *    (amp = A_OMS^2 and A_TM^2).  The TDI prefactor is sin^2(xi) sin^2(2 xi),
+ *    xi = 2 pi f L / c (the second-generation delay polynomial).
+ *  - T_SGWB,c = R_c(f) 3 (H0/h)^2 / (4 pi^2 f^3) with amp = 10^u (f/f_knee)^alpha:
+ *    the power law of Eq. (pl) through Eq. (Sh).
+ *  - T_FG,c = an optional input shape table with amp = 10^u_fg.
+ *  - P_j: Akima spline (App. A) in log10 f, linear for 2 or 3 knots, zero
+ *    when disabled (Eqs. (splines); Sec. "Power spectral density breakdown").
+ *  - logL: the per-bin complex-Wishart term of Sec. "MCMC setup" summed over
+ *    bins (segment averaging over N_k frequencies; N_k = 1 is Whittle), with
+ *    E[D] = S and theta-independent constants dropped.
+ *
+ * Conventions
+ *  - Every pointer is a DEVICE pointer unless marked [host].  Arrays of
+ *    per-channel data are channel-major: X[c * n_bins + k], c = 0 (A), 1 (E), 2 (T).
+ *  - Every call is asynchronous on the given stream (hipStream_t passed as
+ *    void*; NULL = the default stream) and never allocates, frees or
+ *    synchronises, so calls may be captured into a HIP graph.  Only
+ *    lps_create, lps_destroy and lps_get_error synchronise.
+ *  - Ownership: the caller owns every buffer passed in; the library never
+ *    keeps a caller pointer after a call returns.  lps_create copies the
+ *    dataset into memory owned by the context and sizes all workspace for
+ *    max_states, so later calls need no allocation.
+ *  - Errors: structural problems (NULL pointers, sizes, capacity, routing,
+ *    precision) return a status before anything is launched.  Problems of
+ *    individual states (see LPS_ST_*) never abort a call: the state's status
+ *    word gets the bit, its logL is -inf and its gradient is zero.
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LPS_H
+#define LPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lps_ctx lps_ctx;
+
+typedef enum {
+  LPS_OK = 0,
+  LPS_E_NULL = 1,       /* a required pointer is NULL */
+  LPS_E_SHAPE = 2,      /* a size or range argument is out of bounds */
+  LPS_E_CAPACITY = 3,   /* n_states > max_states, or k_max outside [2, 64] */
+  LPS_E_ROUTING = 4,    /* the routing table is not one the kernels implement */
+  LPS_E_PRECISION = 5,  /* unknown precision enum */
+  LPS_E_DEVICE = 6,     /* a HIP runtime call failed */
+  LPS_E_NOMEM = 7,      /* device allocation failed in lps_create */
+  LPS_E_STATE = 8       /* the call needs a state the batch does not provide */
+} lps_status;
+
+typedef enum { LPS_FP64 = 0, LPS_MIXED = 1 } lps_precision;
+
+/* Per-state status bits (0 = valid). */
+#define LPS_ST_COUNT 1u       /* a spline has 1 knot, more than k_max knots, or bad offsets */
+#define LPS_ST_ORDER 2u       /* knot abscissae not strictly increasing */
+#define LPS_ST_COVER 4u       /* the edge knots do not enclose every bin */
+#define LPS_ST_NONFINITE 8u   /* a parameter or knot value is not finite */
+#define LPS_ST_AMPLITUDE 16u  /* A_OMS <= 0 or A_TM <= 0 */
+#define LPS_ST_PSD 32u        /* the total PSD is not finite and positive at some bin */
+
+/* Terms of the routing table. */
+#define LPS_TERM_OMS 0
+#define LPS_TERM_TM 1
+#define LPS_TERM_SGWB 2
+#define LPS_TERM_FG 3
+
+/* Parameter rows of lps_states.params. */
+#define LPS_P_AOMS 0   /* OMS amplitude A_OMS [m Hz^-1/2] */
+#define LPS_P_ATM 1    /* TM amplitude A_TM [m s^-2 Hz^-1/2] */
+#define LPS_P_U 2      /* u = log10 of h^2 Omega at f_knee (Eq. (pl) amplitude A) */
+#define LPS_P_ALPHA 3  /* spectral slope n of Eq. (pl) */
+#define LPS_P_UFG 4    /* log10 of the foreground amplitude (only with a FG table) */
+
+/* The analysed dataset (copied by lps_create). */
+typedef struct {
+  int32_t n_bins;        /* K >= 1 */
+  const double* f;       /* [K] bin frequencies in Hz, strictly increasing, > 0 */
+  const double* nk;      /* [K] N_k >= 1, frequencies averaged into bin k */
+  const double* D;       /* [3][K] averaged periodogram, E[D] = S (one-sided PSD units) */
+  const double* R;       /* [3][K] sky-averaged SGWB response R_c(f_k) (input table) */
+  const double* Rfg;     /* [3][K] foreground shape table, or NULL for no FG term */
+  double f_knee;         /* pivot of the power law in Hz (1e-3) */
+  double arm_length;     /* L in m (2.5e9) */
+  int32_t n_spl;         /* number of spline slots per state, 0..4 */
+  int8_t route[4][3];    /* route[term][channel] = spline slot or -1 (unperturbed);
+                            route[LPS_TERM_FG][*] must be -1 */
+  int32_t k_max;         /* max knots per spline including edges, 2..64 */
+  int32_t max_states;    /* workspace capacity in states (>= 1) */
+} lps_dataset_desc;
+
+/* A batch of states: parameters plus ragged CSR knots (device arrays). */
+typedef struct {
+  int32_t n_states;          /* 0..max_states */
+  const double* params;      /* [P][n_states]; P = 4, or 5 with a FG table */
+  const int32_t* knot_off;   /* [n_states * n_spl + 1]; spline j of state s owns
+                                knots knot_off[s*n_spl+j] .. knot_off[s*n_spl+j+1]-1.
+                                Count 0 disables the spline (P = 0); 2 or 3 is linear;
+                                4..k_max is Akima; 1 is invalid. */
+  const double* knot_x;      /* log10 f of each knot, edges included, strictly increasing */
+  const double* knot_y;      /* knot heights (P is in dex: the factor is 10^P) */
+} lps_states;
+
+/*
+ * Create a context on HIP device `device` for one dataset.  Copies the data,
+ * builds the per-bin tables (template transfer factors, log10 f, scaled
+ * FP32 copies for the mixed path) on the device, and allocates workspace for
+ * desc->max_states states.  Supported routings (any spline slot may be -1):
+ *   split:  OMS, TM, SGWB each on their own channel-independent spline;
+ *   shared: OMS and TM on one channel-independent spline, SGWB on another;
+ *   paper:  OMS and TM on one spline per channel, SGWB on a shared spline
+ *           (the layout of Sec. "Power spectral density breakdown").
+ * Returns LPS_E_ROUTING for any other table.  Synchronises the device.
+ */
+lps_status lps_create(const lps_dataset_desc* desc /*[host]*/, int device, lps_ctx** out /*[host]*/);
+
+/* Free a context and all of its device memory (NULL is a no-op). */
+lps_status lps_destroy(lps_ctx* ctx);
+
+/*
+ * Total PSD (Eq. (psd_tot) with Eqs. (splines)) for bins [k0, k1) of every
+ * state, FP64: S[s][c][k - k0].  Optional Sn (noise: OMS + TM terms) and Sh
+ * (signal: SGWB + FG terms) with the same layout; pass NULL to skip.
+ * Invalid states get NaN rows and their status bits.
+ */
+lps_status lps_psd_build(lps_ctx* ctx, const lps_states* st /*[host]*/, int32_t k0, int32_t k1,
+                         double* S, double* Sn, double* Sh, uint32_t* status, void* stream);
+
+/*
+ * logL[s] for every state in one batched launch.  LPS_FP64 evaluates every
+ * per-bin term in double precision; LPS_MIXED evaluates them in single
+ * precision in per-bin scaled units (hardware exp2/log2/rcp) and keeps the
+ * per-state bin reduction and the scaling constant in double precision.
+ * status (nullable) receives the LPS_ST_* bits.
+ */
+lps_status lps_loglike_batch(lps_ctx* ctx, const lps_states* st /*[host]*/, lps_precision prec,
+                             double* logL, uint32_t* status, void* stream);
+
+/*
+ * logL and its gradient (hand-written adjoint):
+ *   dparams[p][s]   = dlogL/d params[p][s]   (same layout as params)
+ *   dknot_x[i], dknot_y[i] = dlogL/d knot_x[i], knot_y[i] (same CSR layout as
+ *   the knots; edge abscissae get 0 because they are fixed).
+ * Derivatives of |.| at 0 are taken as 0.  Invalid states get zeros.
+ */
+lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st /*[host]*/, lps_precision prec,
+                                  double* logL, double* dparams, double* dknot_x, double* dknot_y,
+                                  uint32_t* status, void* stream);
+
+/*
+ * Reference path: plain FP64, one launch per state, one thread per bin,
+ * every factor evaluated from f_k (sin, cos, pow, exp10, log), a binary
+ * search and a local Akima stencil per bin, and a two-pass reduction.
+ */
+lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st /*[host]*/, double* logL,
+                                  uint32_t* status, void* stream);
+
+/*
+ * Per-kernel timing: when enabled, the forward and gradient entry points
+ * record HIP events around their main kernel on the call's stream.
+ * lps_kernel_time_ms synchronises and returns the summed milliseconds and
+ * launch count of the main kernel since the last reset.  Not graph-safe:
+ * keep it disabled while capturing.
+ */
+lps_status lps_set_timing(lps_ctx* ctx, int enable);
+lps_status lps_kernel_time_ms(lps_ctx* ctx, double* total_ms /*[host]*/, int32_t* launches /*[host]*/);
+
+/* Synchronise the stream and report the sticky device error flags (0 = none). */
+lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags /*[host]*/);
+
+/* Static text for a status code. */
+const char* lps_strerror(lps_status s);
+
+/* Number of bins per wave chunk used by the batched kernels (for sizing checks). */
+int32_t lps_chunk_bins(lps_precision prec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPS_H */

@@ -31,7 +31,9 @@ with x_k = log10 f_k.  Readings of passages that are ambiguous or garbled
       1/2 of C_AET and all theta-independent constants are dropped.
   R8  f_knee = 1e-3 Hz; H0/h = 100 km/s/Mpc = 1e5 / 3.0856775814913673e22 Hz.
   R9  A bin with x_k = x_i lies in interval i ([x_i, x_{i+1})); a bin at the
-      last edge uses the last interval.  The knots must cover every bin.
+      last edge uses the last interval.  The knots must cover every bin (the
+      edge test allows 1e-9 dex so that edges placed at log10 of the first or
+      last bin pass whatever rounding log10 had).
   R10 d|z|/dz at z = 0 is taken as 0 in the gradient.
 """
 from __future__ import annotations
@@ -51,6 +53,7 @@ ST_COVER = 4        # edge knots do not enclose every bin
 ST_NONFINITE = 8    # non-finite parameter or knot value
 ST_AMPLITUDE = 16   # A_oms <= 0 or A_tm <= 0
 ST_PSD = 32         # the total PSD is not finite and positive at some bin
+COVER_SLACK = 1e-9  # dex; tolerance of the edge-enclosure test
 
 TERM_OMS, TERM_TM, TERM_SGWB, TERM_FG = 0, 1, 2, 3
 
@@ -198,7 +201,8 @@ def state_status(ds, params, knots, k_max=64):
             continue
         if np.any(np.diff(kx) <= 0.0):
             st |= ST_ORDER
-        if kx[0] > x_first or kx[-1] < x_last:
+        # edges sit at the band extremes; 1e-9 dex absorbs libm rounding of log10
+        if kx[0] > x_first + COVER_SLACK or kx[-1] < x_last - COVER_SLACK:
             st |= ST_COVER
     return st
 

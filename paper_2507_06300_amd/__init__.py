@@ -1,0 +1,263 @@
+"""MI355X batched flexible-PSD / Whittle log-likelihood (arXiv 2507.06300 hot path).
+
+A thin ctypes binding over the C ABI of ``liblps.so`` (declared in
+``include/lps.h``).  PyTorch provides device memory and streams only; every
+step of the computation runs in the library's HIP kernels.  The names follow
+the ABI: ``psd_build``, ``loglike_batch``, ``loglike_grad_batch``,
+``loglike_plain_fp64``.  If the library is missing the import fails loudly:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblps.so")
+
+FP64 = 0
+MIXED = 1
+_PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+
+ST_COUNT, ST_ORDER, ST_COVER, ST_NONFINITE, ST_AMPLITUDE, ST_PSD = 1, 2, 4, 8, 16, 32
+
+_STATUS_NAMES = {0: "LPS_OK", 1: "LPS_E_NULL", 2: "LPS_E_SHAPE", 3: "LPS_E_CAPACITY", 4: "LPS_E_ROUTING",
+                 5: "LPS_E_PRECISION", 6: "LPS_E_DEVICE", 7: "LPS_E_NOMEM", 8: "LPS_E_STATE"}
+
+
+class LpsError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {_STATUS_NAMES.get(code, code)} ({lib().lps_strerror(code).decode()})")
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("f", ctypes.c_void_p), ("nk", ctypes.c_void_p),
+                ("D", ctypes.c_void_p), ("R", ctypes.c_void_p), ("Rfg", ctypes.c_void_p),
+                ("f_knee", ctypes.c_double), ("arm_length", ctypes.c_double), ("n_spl", ctypes.c_int32),
+                ("route", ctypes.c_int8 * 12), ("k_max", ctypes.c_int32), ("max_states", ctypes.c_int32)]
+
+
+class _States(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("params", ctypes.c_void_p), ("knot_off", ctypes.c_void_p),
+                ("knot_x", ctypes.c_void_p), ("knot_y", ctypes.c_void_p)]
+
+
+SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
+           "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error", "lps_strerror",
+           "lps_chunk_bins"]
+
+_lib = None
+
+
+def lib():
+    """Load liblps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2507_06300_amd.build_lib.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    L.lps_create.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.POINTER(vp)]
+    L.lps_destroy.argtypes = [vp]
+    L.lps_psd_build.argtypes = [vp, ctypes.POINTER(_States), i32, i32, vp, vp, vp, vp, vp]
+    L.lps_loglike_batch.argtypes = [vp, ctypes.POINTER(_States), ctypes.c_int, vp, vp, vp]
+    L.lps_loglike_grad_batch.argtypes = [vp, ctypes.POINTER(_States), ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    L.lps_loglike_plain_fp64.argtypes = [vp, ctypes.POINTER(_States), vp, vp, vp]
+    L.lps_set_timing.argtypes = [vp, ctypes.c_int]
+    L.lps_kernel_time_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    L.lps_get_error.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
+    L.lps_strerror.argtypes = [ctypes.c_int]
+    L.lps_strerror.restype = ctypes.c_char_p
+    L.lps_chunk_bins.argtypes = [ctypes.c_int]
+    L.lps_chunk_bins.restype = ctypes.c_int32
+    for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
+                 "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
+        getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def _check(code, where):
+    if code != 0:
+        raise LpsError(code, where)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class States:
+    """A state batch resident on the device (params [P][n], CSR knots)."""
+    params: torch.Tensor
+    knot_off: torch.Tensor
+    knot_x: torch.Tensor
+    knot_y: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.params.shape[1])
+
+    def _c(self):
+        return _States(self.n, self.params.data_ptr(), self.knot_off.data_ptr(), self.knot_x.data_ptr(),
+                       self.knot_y.data_ptr())
+
+
+class Context:
+    """One analysed dataset on one GPU (wraps lps_create / lps_destroy)."""
+
+    def __init__(self, f, nk, D, R, route, n_spl, Rfg=None, k_max=64, max_states=1, f_knee=1.0e-3,
+                 arm_length=2.5e9, device=None):
+        self.device = torch.device(device if device is not None else "cuda")
+        dev = self.device
+        self.f = _dev(f, torch.float64, dev)
+        self.nk = _dev(nk, torch.float64, dev)
+        self.D = _dev(D, torch.float64, dev)
+        self.R = _dev(R, torch.float64, dev)
+        self.Rfg = None if Rfg is None else _dev(Rfg, torch.float64, dev)
+        self.n_bins = int(self.f.numel())
+        self.n_spl = int(n_spl)
+        self.n_params = 5 if Rfg is not None else 4
+        self.max_states = int(max_states)
+        d = _Desc()
+        d.n_bins = self.n_bins
+        d.f, d.nk, d.D, d.R = (self.f.data_ptr(), self.nk.data_ptr(), self.D.data_ptr(), self.R.data_ptr())
+        d.Rfg = None if self.Rfg is None else self.Rfg.data_ptr()
+        d.f_knee = float(f_knee)
+        d.arm_length = float(arm_length)
+        d.n_spl = self.n_spl
+        flat = [int(v) for row in route for v in row]
+        for i in range(12):
+            d.route[i] = flat[i]
+        d.k_max = int(k_max)
+        d.max_states = self.max_states
+        h = ctypes.c_void_p()
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        _check(lib().lps_create(ctypes.byref(d), idx, ctypes.byref(h)), "lps_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lps_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def states(self, params, knot_off, knot_x, knot_y) -> States:
+        dev = self.device
+        return States(_dev(params, torch.float64, dev), _dev(knot_off, torch.int32, dev),
+                      _dev(knot_x, torch.float64, dev), _dev(knot_y, torch.float64, dev))
+
+    def psd_build(self, st: States, k0=0, k1=None, parts=False, stream=None):
+        k1 = self.n_bins if k1 is None else int(k1)
+        n = st.n
+        S = torch.empty((n, 3, k1 - k0), dtype=torch.float64, device=self.device)
+        Sn = torch.empty_like(S) if parts else None
+        Sh = torch.empty_like(S) if parts else None
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_psd_build(self._h, ctypes.byref(c), int(k0), int(k1), _ptr(S), _ptr(Sn), _ptr(Sh),
+                                   _ptr(status), _stream(stream)), "lps_psd_build")
+        return (S, Sn, Sh, status) if parts else (S, status)
+
+    def loglike_batch(self, st: States, precision="fp64", out=None, status=None, stream=None):
+        n = st.n
+        logL = out if out is not None else torch.empty(n, dtype=torch.float64, device=self.device)
+        status = status if status is not None else torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_loglike_batch(self._h, ctypes.byref(c), _PREC.get(precision, precision), _ptr(logL), _ptr(status),
+                                       _stream(stream)), "lps_loglike_batch")
+        return logL, status
+
+    def loglike_grad_batch(self, st: States, precision="fp64", stream=None):
+        n = st.n
+        logL = torch.empty(n, dtype=torch.float64, device=self.device)
+        dparams = torch.empty((self.n_params, n), dtype=torch.float64, device=self.device)
+        dkx = torch.empty_like(st.knot_x)
+        dky = torch.empty_like(st.knot_y)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_loglike_grad_batch(self._h, ctypes.byref(c), _PREC.get(precision, precision), _ptr(logL), _ptr(dparams),
+                                            _ptr(dkx), _ptr(dky), _ptr(status), _stream(stream)),
+               "lps_loglike_grad_batch")
+        return logL, dparams, dkx, dky, status
+
+    def loglike_plain_fp64(self, st: States, stream=None):
+        n = st.n
+        logL = torch.empty(n, dtype=torch.float64, device=self.device)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_loglike_plain_fp64(self._h, ctypes.byref(c), _ptr(logL), _ptr(status), _stream(stream)),
+               "lps_loglike_plain_fp64")
+        return logL, status
+
+    def set_timing(self, on: bool):
+        _check(lib().lps_set_timing(self._h, 1 if on else 0), "lps_set_timing")
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        _check(lib().lps_kernel_time_ms(self._h, ctypes.byref(ms), ctypes.byref(n)), "lps_kernel_time_ms")
+        return ms.value, n.value
+
+    def get_error(self, stream=None):
+        v = ctypes.c_uint32()
+        _check(lib().lps_get_error(self._h, _stream(stream), ctypes.byref(v)), "lps_get_error")
+        return v.value
+
+
+def chunk_bins(precision="fp64") -> int:
+    return int(lib().lps_chunk_bins(_PREC.get(precision, precision)))
+
+
+class LogLikeFn(torch.autograd.Function):
+    """logL(theta) with the library's adjoint as its backward.
+
+    forward(ctx_obj, precision, params, knot_x, knot_y, knot_off) -> logL [n]
+    Gradients flow to params, knot_x and knot_y.
+    """
+
+    @staticmethod
+    def forward(fctx, lctx: Context, precision, params, knot_x, knot_y, knot_off):
+        st = States(params.detach().contiguous(), knot_off.contiguous(), knot_x.detach().contiguous(),
+                    knot_y.detach().contiguous())
+        logL, dp, dkx, dky, _ = lctx.loglike_grad_batch(st, precision)
+        fctx.save_for_backward(dp, dkx, dky, knot_off)
+        fctx.n_spl = lctx.n_spl
+        return logL
+
+    @staticmethod
+    def backward(fctx, gout):
+        dp, dkx, dky, knot_off = fctx.saved_tensors
+        n = dp.shape[1]
+        n_spl = fctx.n_spl
+        # per-knot state index from the CSR offsets: knots of state s lie in [off[s*n_spl], off[(s+1)*n_spl])
+        counts = (knot_off[n_spl::n_spl][:n] - knot_off[0:n * n_spl:n_spl]).to(torch.int64)
+        owner = torch.repeat_interleave(torch.arange(n, device=dp.device), counts)
+        g_knot = gout[owner]
+        return None, None, dp * gout[None, :], dkx * g_knot, dky * g_knot, None

@@ -1,0 +1,51 @@
+// Per-state validation shared by every entry point.
+//
+// A state is valid when its parameters are finite, A_OMS > 0 and A_TM > 0,
+// and every spline slot holds 0 knots (disabled) or 2..k_max knots whose
+// abscissae are finite, strictly increasing and enclose the analysed band
+// (edge knots at the band extremes, Sec. "Power spectral density breakdown").
+// The enclosure test allows 1e-9 dex of slack so that an edge knot placed at
+// log10 of the first or last bin frequency passes whatever libm rounded.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lps.h"
+
+namespace lps {
+
+constexpr double kCoverSlack = 1e-9;
+
+__device__ inline uint32_t validate_state(int s, int n_states, int n_spl, int k_max, int n_params,
+                                          const double* __restrict__ params, const int32_t* __restrict__ off,
+                                          const double* __restrict__ kx, const double* __restrict__ ky,
+                                          double x_first, double x_last) {
+  uint32_t st = 0;
+  for (int p = 0; p < n_params; ++p)
+    if (!isfinite(params[p * (size_t)n_states + s])) st |= LPS_ST_NONFINITE;
+  const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
+  const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
+  if (!(a_oms > 0.0 && a_tm > 0.0)) st |= LPS_ST_AMPLITUDE;
+  for (int j = 0; j < n_spl; ++j) {
+    const int a = off[s * n_spl + j];
+    const int cnt = off[s * n_spl + j + 1] - a;
+    if (cnt == 0) continue;
+    if (a < 0 || cnt < 0 || cnt == 1 || cnt > k_max) {
+      st |= LPS_ST_COUNT;
+      continue;
+    }
+    bool fin = true;
+    for (int i = 0; i < cnt; ++i) fin = fin && isfinite(kx[a + i]) && isfinite(ky[a + i]);
+    if (!fin) {
+      st |= LPS_ST_NONFINITE;
+      continue;
+    }
+    for (int i = 0; i + 1 < cnt; ++i)
+      if (!(kx[a + i + 1] > kx[a + i])) st |= LPS_ST_ORDER;
+    if (kx[a] > x_first + kCoverSlack || kx[a + cnt - 1] < x_last - kCoverSlack) st |= LPS_ST_COVER;
+  }
+  return st;
+}
+
+}  // namespace lps

@@ -1,0 +1,235 @@
+"""GPU parity: HIP path vs the FP64 oracle on the same seeded inputs.
+
+FP64 paths:   |dlogL| <= 1e-9 |logL|          (the stated FP64 tolerance)
+mixed path:   |dlogL| <= derived bound          (tests/cases.mixed_tolerance)
+psd_build:    elementwise relative 1e-12
+status words: bit-exact
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import lps_oracle as O  # noqa: E402
+from synth import workloads as W  # noqa: E402
+from tests import cases as C  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_06300_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+LAYOUT_CASES = [
+    # (workload recipe, layout, bins, states, in-between range)
+    ("grad_25000bins_1024states", "split", 3001, 37, (0, 12)),
+    ("avg50_1000bins_64states", "noise_signal", 1000, 64, (4, 4)),
+    ("grad_25000bins_1024states", "paper", 2333, 29, (0, 10)),
+    ("sweep_250000bins_2048chains", "split_fg", 2777, 33, (0, 40)),
+    ("daily_2497bins_320states", "split", 2497, 45, (2, 20)),
+]
+
+
+def _case(name, layout, n_bins, n_states, inbetween):
+    ds, D = C.dataset_with_data(name, n_bins=n_bins, layout=layout)
+    sb = W.make_states(name, ds, n_states=n_states, inbetween=inbetween)
+    return ds, D, sb
+
+
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=[f"{c[1]}-{c[2]}" for c in LAYOUT_CASES])
+def test_fp64_batched_and_plain_match_oracle(lps, case):
+    _say("case", case)
+    ds, D, sb = _case(*case)
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    ref = C.oracle_loglikes(ds, D, sb)
+    got, status = ctx.loglike_batch(st, "fp64")
+    got = got.cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    rel = np.abs(got - ref) / np.abs(ref)
+    _say("fp64 batched max rel err", rel.max())
+    assert rel.max() <= 1e-9
+    plain, pst = ctx.loglike_plain_fp64(st)
+    plain = plain.cpu().numpy()
+    relp = np.abs(plain - ref) / np.abs(ref)
+    _say("plain fp64 max rel err", relp.max())
+    assert relp.max() <= 1e-9
+    assert np.all(pst.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=[f"{c[1]}-{c[2]}" for c in LAYOUT_CASES])
+def test_mixed_matches_oracle_within_derived_bound(lps, case):
+    _say("case", case)
+    ds, D, sb = _case(*case)
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    ref = C.oracle_loglikes(ds, D, sb)
+    got, status = ctx.loglike_batch(st, "mixed")
+    got = got.cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    err = np.abs(got - ref)
+    tol = C.mixed_tolerance(ds, D, sb, range(sb.n))
+    _say("mixed max abs err", err.max(), "max rel", (err / np.abs(ref)).max(), "min tol", tol.min())
+    assert np.all(err <= tol)
+    # differences between states (what a Metropolis step uses)
+    d_got = got[1:] - got[0]
+    d_ref = ref[1:] - ref[0]
+    _say("mixed max err of logL differences", np.abs(d_got - d_ref).max())
+    assert np.all(np.abs(d_got - d_ref) <= tol[1:] + tol[0])
+
+
+@pytest.mark.parametrize("layout", ["split", "paper", "split_fg", "noise_signal"])
+def test_psd_build_matches_oracle(lps, layout):
+    name = "sweep_250000bins_2048chains" if layout == "split_fg" else "grad_25000bins_1024states"
+    _say("psd", layout)
+    ds, D = C.dataset_with_data(name, n_bins=1500, layout=layout)
+    sb = W.make_states(name, ds, n_states=7, inbetween=(0, 12))
+    ctx = C.make_context(lps, ds, D, max_states=8)
+    st = C.device_states(ctx, sb)
+    S, Sn, Sh, status = ctx.psd_build(st, parts=True)
+    assert np.all(status.cpu().numpy() == 0)
+    S, Sn, Sh = S.cpu().numpy(), Sn.cpu().numpy(), Sh.cpu().numpy()
+    for s in range(sb.n):
+        rS, rSn, rSh = O.psd(ds, sb.params[:, s], C.knots_of(sb, s))
+        np.testing.assert_allclose(S[s], rS, rtol=1e-12)
+        np.testing.assert_allclose(Sn[s], rSn, rtol=1e-12)
+        np.testing.assert_allclose(Sh[s], rSh, rtol=1e-12, atol=1e-300)
+    # a bin sub-range
+    S2, _ = ctx.psd_build(st, k0=100, k1=733)
+    np.testing.assert_array_equal(S2.cpu().numpy(), S[:, :, 100:733])
+
+
+def test_knot_count_edge_cases(lps):
+    """Counts 0 (disabled), 2 and 3 (linear), 4 (smallest Akima), k_max; knots on bins."""
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=1024 + 77, layout="split")
+    x = np.log10(ds.f)
+    x_lo, x_hi = x[0], x[-1]
+    rng = np.random.default_rng(3)
+    k_max = 64
+    knots = []
+    params = []
+    counts = [0, 2, 3, 4, 5, 17, k_max]
+    for s, n in enumerate(counts * 2):
+        row = []
+        for j in range(3):
+            nn = counts[(s + j) % len(counts)]
+            if nn == 0:
+                row.append((np.zeros(0), np.zeros(0)))
+                continue
+            if s >= len(counts) and nn > 2:
+                # interior knots exactly on bin abscissae
+                inner = np.sort(rng.choice(x[1:-1], nn - 2, replace=False))
+            else:
+                inner = np.sort(rng.uniform(x_lo, x_hi, nn - 2))
+            row.append((np.concatenate([[x_lo], inner, [x_hi]]), rng.normal(0, 0.1, nn)))
+        knots.append(row)
+        params.append([rng.uniform(10, 20) * 1e-12, rng.uniform(2, 4) * 1e-15, rng.uniform(-13, -11),
+                       rng.uniform(-1, 1)])
+    sb = W.pack_states(np.array(params).T, knots, 3)
+    ctx = C.make_context(lps, ds, D, max_states=sb.n, k_max=k_max)
+    st = C.device_states(ctx, sb)
+    ref = C.oracle_loglikes(ds, D, sb)
+    got64 = ctx.loglike_batch(st, "fp64")[0].cpu().numpy()
+    gotm = ctx.loglike_batch(st, "mixed")[0].cpu().numpy()
+    gotp = ctx.loglike_plain_fp64(st)[0].cpu().numpy()
+    assert np.all(np.abs(got64 - ref) <= 1e-9 * np.abs(ref))
+    assert np.all(np.abs(gotp - ref) <= 1e-9 * np.abs(ref))
+    assert np.all(np.abs(gotm - ref) <= C.mixed_tolerance(ds, D, sb, range(sb.n)))
+
+
+def test_invalid_states_status_and_minus_inf(lps):
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=900, layout="split")
+    sb = W.make_states(name, ds, n_states=8, inbetween=(2, 6))
+    params = sb.params.copy()
+    knots = [C.knots_of(sb, s) for s in range(sb.n)]
+    knots = [[(x.copy(), y.copy()) for (x, y) in row] for row in knots]
+    x0, y0 = knots[0][0]
+    knots[0][0] = (x0[::-1].copy(), y0)                               # unsorted
+    knots[1][1] = (np.array([-3.0]), np.array([0.1]))                 # one knot
+    x2, y2 = knots[2][2]
+    knots[2][2] = (x2[1:].copy(), y2[1:].copy())                      # does not cover the band
+    params[0, 3] = -1.0                                               # A_oms <= 0
+    params[3, 4] = float("nan")                                       # non-finite alpha
+    x5, y5 = knots[5][0]
+    y5 = y5.copy()
+    y5[1] = float("inf")
+    knots[5][0] = (x5, y5)                                            # non-finite height
+    bad = W.pack_states(params, knots, 3)
+    ctx = C.make_context(lps, ds, D, max_states=bad.n)
+    st = C.device_states(ctx, bad)
+    ref_status = C.oracle_status(ds, bad)
+    ref = C.oracle_loglikes(ds, D, bad)
+    for prec in ("fp64", "mixed"):
+        logL, status = ctx.loglike_batch(st, prec)
+        np.testing.assert_array_equal(status.cpu().numpy(), ref_status)
+        got = logL.cpu().numpy()
+        assert np.all(np.isneginf(got[ref_status != 0]))
+        ok = ref_status == 0
+        assert np.all(np.abs(got[ok] - ref[ok]) <= np.abs(ref[ok]) * (1e-9 if prec == "fp64" else 1e-6))
+    plain, pst = ctx.loglike_plain_fp64(st)
+    np.testing.assert_array_equal(pst.cpu().numpy(), ref_status)
+    assert np.all(np.isneginf(plain.cpu().numpy()[ref_status != 0]))
+
+
+def test_empty_batch_and_structural_errors(lps):
+    ds, D = C.dataset_with_data("grad_25000bins_1024states", n_bins=300, layout="split")
+    ctx = C.make_context(lps, ds, D, max_states=4)
+    sb = W.make_states("grad_25000bins_1024states", ds, n_states=5)
+    st = C.device_states(ctx, sb)
+    with pytest.raises(lps.LpsError) as e:
+        ctx.loglike_batch(st, "fp64")
+    assert e.value.code == 3   # capacity
+    sub = W.states_subset(sb, [])
+    empty = ctx.states(np.zeros((4, 0)), np.zeros(1, np.int32), np.zeros(1), np.zeros(1))
+    logL, status = ctx.loglike_batch(empty, "mixed")
+    assert logL.numel() == 0
+    with pytest.raises(lps.LpsError):
+        ctx.loglike_batch(C.device_states(ctx, W.states_subset(sb, [0, 1])), 7)
+    assert sub.n == 0
+
+
+def test_repeatable_and_graph_replay(lps):
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=5000, layout="split")
+    sb = W.make_states(name, ds, n_states=100, inbetween=(0, 20))
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    for prec in ("fp64", "mixed"):
+        a = ctx.loglike_batch(st, prec)[0].clone()
+        b = ctx.loglike_batch(st, prec)[0].clone()
+        assert torch.equal(a, b)
+        out = torch.empty_like(a)
+        status = torch.empty(sb.n, dtype=torch.int32, device=a.device)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            ctx.loglike_batch(st, prec, out=out, status=status)   # warm up on the capture stream
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.loglike_batch(st, prec, out=out, status=status)
+        for rep in range(3):
+            out.fill_(0.0)
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, a), (prec, rep)
+            # eager work between replays
+            c = ctx.loglike_batch(st, prec)[0]
+            assert torch.equal(c, a)
