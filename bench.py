@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Throughput of the batched flexible-PSD / Whittle log-likelihood on one MI355X.
+
+One step = one batched logL evaluation (mixed precision: FP32 per-bin terms,
+FP64 per-state reduction) of every state of the workload, inputs resident in
+HBM, replayed from a captured HIP graph.  The default workload is the full
+one-year unaveraged periodogram (912,085 bins x 3 channels, N_k = 1) with
+4,096 states (64 walkers x 16 temperatures x 4 reversible-jump branches).
+
+Printed: one JSON line with the headline value (state.bin evals/s of the
+mixed batched path) plus, measured in the same run on the same GPU, the FP64
+batched path, the plain FP64 per-state path (on a stated state sample), the
+mixed-vs-FP64 error per result, the ALU roofline of the dominant kernel, and
+the FP64 CPU oracle timed on a bounded sample of the host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "logL state·bin evals/s, batched mixed vs plain FP64 (same GPU); grad evals/s"
+UNIT = "state·bin evals/s"
+
+# Algorithmic VALU work of the mixed batched kernel per state.bin for the
+# split layout with A and E merged (3 exponent groups, 2 distinct channels):
+#   per group   : t = x + off (1), Horner (3 FMA), exp2 (1 transcendental)
+#   assembly    : 2 channels x (1 mul + 2 FMA)
+#   likelihood  : 2 channels x (rcp, log2 transcendentals + 2 FMA)
+#   accumulate  : cvt f32->f64 + f64 add
+#   per group   : t = x + off, 3-FMA Horner, exp2                  -> 4 + 1 trans
+#   assembly    : 2 channels x 3 groups, one FMA each                -> 6
+#   likelihood  : P = S0 S1, num (mul + fma), rcp(P), log2(P S0),
+#                 v = num r + NL lg (mul + fma)                        -> 6 + 2 trans
+#   accumulate  : cvt f32->f64 + f64 add                              -> 2 x 2 slots
+MIXED_FP32_OPS = 3 * 4 + 6 + 6                      # 24 FP32 VALU instructions
+MIXED_FP64_SLOTS = 2 * 2                             # cvt + add at half rate
+MIXED_TRANS_OPS = 3 + 2                              # exp2 x3, rcp, log2
+
+# Published MI355X FP32 vector peak: 157.3 TFLOP/s = 256 CUs x 128 FP32 FMA
+# lanes/clock x 2 FLOP x 2.4 GHz.  gfx950 reaches this rate with ordinary
+# (non-packed) v_fma_f32 (measured: ~113 lanes/clock/CU on a dependent-chain
+# microbenchmark), so it is the ceiling for this library's FP32 code.
+# Work is counted in FP32-FMA issue slots: FP32 add/mul/fma = 1, FP64 add and
+# FP32<->FP64 conversion = 2 (half rate), transcendental = measured cost.
+PEAK_FMA_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="year_912085bins_4096states")
+    p.add_argument("--plain-states", type=int, default=64,
+                   help="states timed on the plain FP64 per-state path (per-state cost is uniform)")
+    p.add_argument("--cpu-states", type=int, default=48, help="states in the CPU oracle sample")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-grad", action="store_true")
+    p.add_argument("--grad-workload", default="grad_25000bins_1024states")
+    return p.parse_args()
+
+
+def timed_graph(torch, fn, steps, warmup):
+    """Capture fn() into a graph, replay warmup + steps times; returns seconds for `steps`."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(1, warmup)):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3, g
+
+
+def cpu_baseline(name, n_states, dataset_bins=None):
+    """Time the FP64 oracle on a bounded sample of the workload (CPU leg)."""
+    from oracle import lps_oracle as O
+    from synth import workloads as W
+    ds = W.make_dataset(name)
+    truth = [ds.truth.knots(0, j) for j in range(ds.n_spl)]
+    S0, _, _ = O.psd(ds, ds.truth.params[:, 0], truth)
+    D = S0 * ds.chi
+    sb = W.make_states(name, ds)
+    idx = list(range(min(n_states, sb.n)))
+    t0 = time.perf_counter()
+    for s in idx:
+        O.loglike(ds, D, sb.params[:, s], [sb.knots(s, j) for j in range(sb.n_spl)])
+    dt = time.perf_counter() - t0
+    K = ds.f.size
+    return {"value": len(idx) * K / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{len(idx)} of {sb.n} states x {K} bins x 3 channels of {name} "
+                      f"(numpy FP64, single thread), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by walker; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2507_06300_amd as lps
+    from synth import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    name = args.workload
+    wl = W.WORKLOADS[name]
+    ds = W.make_dataset(name)
+    sb = W.make_states(name, ds)
+    K, n = ds.f.size, sb.n
+    log(f"workload {name}: {K} bins x {n} states ({wl.note})")
+
+    # Data: D = S(truth) * chi, with S(truth) from the library's own psd_build.
+    ctx0 = lps.Context(ds.f, ds.nk, np.ones((3, K)), ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg,
+                       max_states=1, device=dev)
+    S0, _ = ctx0.psd_build(ctx0.states(ds.truth.params, ds.truth.knot_off, ds.truth.knot_x, ds.truth.knot_y))
+    D = S0[0] * torch.as_tensor(ds.chi, device=dev)
+    ctx0.close()
+    ctx = lps.Context(ds.f, ds.nk, D, ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=n, device=dev)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+
+    # --- headline: mixed batched, graph-replayed -------------------------------
+    log("mixed batched ...")
+    t_mixed, _ = timed_graph(torch, lambda: ctx.loglike_batch(st, "mixed", out=out, status=status),
+                             args.steps, args.warmup)
+    logL_mixed = out.clone()
+    n_bad = int((status != 0).sum().item())
+    ms_mixed = t_mixed / args.steps * 1e3
+    value = n * K / (t_mixed / args.steps)
+    log(f"  {ms_mixed:.3f} ms/call, {value:.3e} state.bin/s, invalid states {n_bad}")
+
+    # --- FP64 batched ------------------------------------------------------------
+    log("fp64 batched ...")
+    steps64 = max(3, args.steps // 4)
+    t64, _ = timed_graph(torch, lambda: ctx.loglike_batch(st, "fp64", out=out, status=status), steps64, 1)
+    logL64 = out.clone()
+    fp64_value = n * K / (t64 / steps64)
+    log(f"  {t64 / steps64 * 1e3:.3f} ms/call, {fp64_value:.3e} state.bin/s")
+
+    # error of the mixed path, per result, against the FP64 batched path
+    lm, l64 = logL_mixed.cpu().numpy(), logL64.cpu().numpy()
+    both = np.isfinite(lm) & np.isfinite(l64)
+    d = lm[both] - l64[both]
+    ref = l64[both]
+    i0 = int(np.nonzero(both)[0][0])
+    dd = (lm[both] - lm[i0]) - (l64[both] - l64[i0])
+    mixed_err = {"vs": "fp64 batched (oracle-checked)", "states_compared": int(both.sum()),
+                 "invalid_fp64": int((~np.isfinite(l64)).sum()), "invalid_mixed": int((~np.isfinite(lm)).sum()),
+                 "max_abs": float(np.abs(d).max()), "median_abs": float(np.median(np.abs(d))),
+                 "p99_abs": float(np.quantile(np.abs(d), 0.99)), "max_rel": float(np.max(np.abs(d) / np.abs(ref))),
+                 "max_abs_logL_difference": float(np.abs(dd).max())}
+
+    # --- dominant kernel duration (HIP events around the main kernel) ----------
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        ctx.loglike_batch(st, "mixed", out=out, status=status)
+    kms, nl = ctx.kernel_time()
+    ctx.set_timing(False)
+    k_avg_ms = kms / nl
+    fma_ns, trans_cost, lane_rate = lps.valu_probe(0)
+    slots = MIXED_FP32_OPS + MIXED_FP64_SLOTS + MIXED_TRANS_OPS * trans_cost
+    achieved = n * K * slots * 2.0 / (k_avg_ms * 1e-3) / 1e12     # FMA-equivalent TFLOP/s
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FMA_TFLOPS, 4), "traffic": None,
+                "kernel": "k_forward<float,split,AE-merged>", "kernel_ms": round(k_avg_ms, 4),
+                "slots_per_state_bin": round(slots, 2), "trans_cost_fma_slots": round(trans_cost, 3),
+                "measured_fma_lane_instr_per_s": lane_rate}
+    log(f"  main kernel {k_avg_ms:.3f} ms, {achieved:.1f} TFLOP/s-eq ({achieved / PEAK_FMA_TFLOPS:.1%}), "
+        f"trans cost {trans_cost:.2f} slots, fma rate {lane_rate:.3e}")
+
+    result = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": ms_mixed, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+              "config": {"workload": name, "n_bins": K, "n_states": n, "channels": 3,
+                         "N_k": wl.nk, "in_between_knots": list(wl.inbetween), "layout": ds.layout,
+                         "precision": "mixed"},
+              "roofline": roofline,
+              "fp64_batched": {"value": fp64_value, "unit": UNIT, "ms_per_call": t64 / steps64 * 1e3},
+              "mixed_error": mixed_err}
+
+    # --- plain FP64 per-state path on a state sample ---------------------------
+    if not args.no_plain:
+        m = min(args.plain_states, n)
+        from synth.workloads import states_subset
+        sub = states_subset(sb, range(m))
+        stp = ctx.states(sub.params, sub.knot_off, sub.knot_x, sub.knot_y)
+        ctx.loglike_plain_fp64(stp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lp, _ = ctx.loglike_plain_fp64(stp)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        plain_value = m * K / tp
+        err_plain = float((lp - logL64[:m]).abs().max().item())
+        result["plain_fp64"] = {"value": plain_value, "unit": UNIT, "sample_states": m,
+                                "s_per_call": tp, "max_abs_diff_vs_fp64_batched": err_plain}
+        result["speedup_mixed_vs_plain"] = value / plain_value
+        result["speedup_fp64_batched_vs_plain"] = fp64_value / plain_value
+        log(f"plain fp64: {plain_value:.3e} state.bin/s on {m} states; mixed speedup {value / plain_value:.1f}x")
+
+    # --- gradient -----------------------------------------------------------------
+    if not args.no_grad:
+        try:
+            result["grad"] = grad_bench(torch, lps, W, args, dev)
+        except lps.LpsError as e:
+            result["grad"] = {"error": str(e)}
+
+    # --- CPU oracle baseline ------------------------------------------------------
+    if not args.no_cpu:
+        log("cpu oracle sample ...")
+        result["cpu_baseline"] = cpu_baseline(name, args.cpu_states)
+        log(f"  {result['cpu_baseline']['value']:.3e} state.bin/s")
+
+    print(json.dumps(result), flush=True)
+
+
+def grad_bench(torch, lps, W, args, dev):
+    name = args.grad_workload
+    ds = W.make_dataset(name)
+    sb = W.make_states(name, ds)
+    K, n = ds.f.size, sb.n
+    ctx0 = lps.Context(ds.f, ds.nk, np.ones((3, K)), ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg,
+                       max_states=1, device=dev)
+    S0, _ = ctx0.psd_build(ctx0.states(ds.truth.params, ds.truth.knot_off, ds.truth.knot_x, ds.truth.knot_y))
+    D = S0[0] * torch.as_tensor(ds.chi, device=dev)
+    ctx0.close()
+    ctx = lps.Context(ds.f, ds.nk, D, ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=n, device=dev)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    res = {"workload": name, "n_bins": K, "n_states": n}
+    for prec in ("mixed", "fp64"):
+        steps = max(3, args.steps // 2)
+        t, _ = timed_graph(torch, lambda: ctx.loglike_grad_batch(st, prec), steps, 1)
+        per = t / steps
+        res[prec] = {"grad_evals_per_s": n / per, "state_bin_grad_evals_per_s": n * K / per,
+                     "ms_per_call": per * 1e3}
+        log(f"grad {prec}: {per * 1e3:.3f} ms/call, {n / per:.3e} grad evals/s")
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -188,6 +188,16 @@ const char* lps_strerror(lps_status s);
 /* Number of bins per wave chunk used by the batched kernels (for sizing checks). */
 int32_t lps_chunk_bins(lps_precision prec);
 
+/*
+ * Device calibration for roofline reporting (not part of the hot path):
+ * times a dependent FP32 FMA chain and an exp2/log2/rcp chain on every CU.
+ * Outputs [host]: nanoseconds per wave64 FMA instruction per SIMD, the issue
+ * cost of one single-precision transcendental in FMA slots, and the achieved
+ * FP32 lane-instruction rate of the whole device.  Allocates and synchronises.
+ */
+lps_status lps_valu_probe(int device, double* fma_ns_per_wave_instr, double* trans_over_fma,
+                          double* lane_instr_per_s);
+
 #ifdef __cplusplus
 }
 #endif

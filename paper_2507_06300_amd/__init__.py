@@ -50,7 +50,7 @@ class _States(ctypes.Structure):
 
 SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
            "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error", "lps_strerror",
-           "lps_chunk_bins"]
+           "lps_chunk_bins", "lps_valu_probe"]
 
 _lib = None
 
@@ -77,6 +77,9 @@ def lib():
     L.lps_strerror.restype = ctypes.c_char_p
     L.lps_chunk_bins.argtypes = [ctypes.c_int]
     L.lps_chunk_bins.restype = ctypes.c_int32
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.lps_valu_probe.argtypes = [ctypes.c_int, dp, dp, dp]
+    L.lps_valu_probe.restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
         getattr(L, name).restype = st
@@ -229,6 +232,13 @@ class Context:
         v = ctypes.c_uint32()
         _check(lib().lps_get_error(self._h, _stream(stream), ctypes.byref(v)), "lps_get_error")
         return v.value
+
+
+def valu_probe(device=0):
+    """(ns per wave64 FMA per SIMD, transcendental cost in FMA slots, lane-instr/s)."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().lps_valu_probe(int(device), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "lps_valu_probe")
+    return a.value, b.value, c.value
 
 
 def chunk_bins(precision="fp64") -> int:

@@ -45,20 +45,29 @@ struct Groups {
   static constexpr int G = MODE == kSplit ? 3 : (MODE == kShared ? 2 : 4);
 };
 
-// S~_c for one bin from the group factors E and the template rows.
-template <typename R, int MODE, int NCH, bool FG, int B>
-__device__ inline R assemble(int c, int b, const R (&Kt)[FG ? 4 : 3][NCH][B], const R (&E)[Groups<MODE>::G][B],
-                             R w_oms, R w_tm, R e_fg) {
-  R S;
-  if constexpr (MODE == kSplit) {
-    S = Kt[0][c][b] * E[0][b] + Kt[1][c][b] * E[1][b] + Kt[2][c][b] * E[2][b];
-  } else if constexpr (MODE == kShared) {
-    S = (w_oms * Kt[0][c][b] + w_tm * Kt[1][c][b]) * E[0][b] + Kt[2][c][b] * E[1][b];
-  } else {
-    S = (w_oms * Kt[0][c][b] + w_tm * Kt[1][c][b]) * E[c][b] + Kt[2][c][b] * E[3][b];
+template <typename R>
+__device__ inline R readlane_r(R v, int lane);
+template <>
+__device__ inline float readlane_r<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <>
+__device__ inline double readlane_r<double>(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Number of interior breakpoints bx[1 .. ni-1] that are <= v (binary search).
+__device__ inline int count_le(const double* __restrict__ bxs, int ni, double v) {
+  int lo = 0, hi = ni - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (bxs[1 + mid] <= v) lo = mid + 1;
+    else hi = mid;
   }
-  if constexpr (FG) S += Kt[3][c][b] * e_fg;
-  return S;
+  return lo;
 }
 
 template <typename R, int MODE, int NCH, bool FG, int B>
@@ -71,9 +80,11 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   constexpr int G = Groups<MODE>::G;
   constexpr int NT = FG ? 4 : 3;
   constexpr int CH = kWave * B;
+  constexpr int SUB = kWave / G;            // states whose pieces one wave locates at once
   constexpr bool kMixed = sizeof(R) == 4;
   const int lane = threadIdx.x & (kWave - 1);
-  const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  // wave-uniform work-item index: keeps all per-state addressing scalar
+  const int item = blockIdx.x * kWavesPerBlock + uniform(threadIdx.x >> 6);
   const int chunk = item % n_chunks;
   const int t = item / n_chunks;
   if (t >= n_tiles) return;
@@ -101,58 +112,140 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   const double xf = x64[kbase];
   const double xl = x64[klast];
 
-  for (int s = s_begin; s < s_end; ++s) {
-    if (n_int[s * G] == 0) {   // invalid state: reported by the finaliser
-      if (lane == 0) partial[(size_t)s * n_chunks + chunk] = 0.0;
-      continue;
+  for (int sub = s_begin; sub < s_end; sub += SUB) {
+    const int nsub = min(SUB, s_end - sub);
+    // ---- locate: lane p owns the piece of (state sub + p / G, group p % G) ----
+    const int ps = lane / G, pg = lane - (lane / G) * G;
+    const bool pv = ps < nsub;
+    const size_t pbase = (size_t)((sub + ps) * G + pg) * kMaxKnots;
+    const int pni = pv ? n_int[(sub + ps) * G + pg] : 0;
+    int pi0 = 0, pi1 = 0;
+    R pa = 0, pb = 0, pc = 0, pd = 0, poff = 0;
+    if (pni > 0) {
+      pi0 = count_le(bx + pbase, pni, xf);
+      pi1 = count_le(bx + pbase, pni, xl);
+      const R* cf = coef + (pbase + pi0) * 4;
+      pa = cf[0];
+      pb = cf[1];
+      pc = cf[2];
+      pd = cf[3];
+      const double b0 = bx[pbase + pi0];
+      poff = kMixed ? (R)(xf - b0) : (R)(-b0);
     }
-    R E[G][B];
+    // per-state scalars on the lanes of group 0
+    R pw0 = 0, pw1 = 0, pw2 = 0;
+    if (pv && pg == 0) {
+      const StateScalars sc = scal[sub + ps];
+      pw0 = (R)sc.w_oms;
+      pw1 = (R)sc.w_tm;
+      pw2 = (R)sc.e_fg;
+    }
+
+    for (int q = 0; q < nsub; ++q) {
+      const int s = sub + q;
+      if (__builtin_amdgcn_readlane(pni, q * G) == 0) {   // invalid state: the finaliser reports it
+        if (lane == 0) partial[(size_t)s * n_chunks + chunk] = 0.0;
+        continue;
+      }
+      const R w_oms = readlane_r(pw0, q * G), w_tm = readlane_r(pw1, q * G), e_fg = readlane_r(pw2, q * G);
+      R S[NCH][B];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const size_t base = (size_t)(s * G + g) * kMaxKnots;
-      const int ni = n_int[s * G + g];
-      const double bl = (lane + 1 < ni) ? bx[base + lane + 1] : INFINITY;
-      const int i0 = __popcll(__ballot(bl <= xf));
-      const int i1 = __popcll(__ballot(bl <= xl));
-      if (i0 == i1) {
-        const R* cf = coef + (base + i0) * 4;
-        const R a = cf[0], bb = cf[1], c = cf[2], d = cf[3];
-        const double b0 = bx[base + i0];
-        const R off = kMixed ? (R)(xf - b0) : (R)(-b0);
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int b = 0; b < B; ++b) S[c][b] = FG ? Kt[3][c][b] * e_fg : (R)0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int pl = q * G + g;
+        const int i0 = __builtin_amdgcn_readlane(pi0, pl);
+        const int i1 = __builtin_amdgcn_readlane(pi1, pl);
+        R E[B];
+        if (i0 == i1) {   // the chunk lies in one piece: wave-uniform coefficients
+          const R a = readlane_r(pa, pl), bb = readlane_r(pb, pl), cc = readlane_r(pc, pl),
+                  dd = readlane_r(pd, pl), off = readlane_r(poff, pl);
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            const R tt = xr[b] + off;
+            E[b] = Math<R>::exp2_(a + tt * (bb + tt * (cc + tt * dd)));
+          }
+        } else {          // a breakpoint falls inside the chunk: evaluate each piece, select per bin
+          const size_t base = (size_t)(s * G + g) * kMaxKnots;
+          R Q[B];
+          for (int j = i0; j <= i1; ++j) {
+            const R* cf = coef + (base + j) * 4;
+            const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
+            const double bj = bx[base + j];
+            const R off = kMixed ? (R)(xf - bj) : (R)(-bj);
+            const R lim = kMixed ? (R)(bj - xf) : (R)bj;   // bin is in piece j when xr >= lim
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+              const R tt = xr[b] + off;
+              const R qv = a + tt * (bb + tt * (cc + tt * dd));
+              Q[b] = (j == i0 || xr[b] >= lim) ? qv : Q[b];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(Q[b]);
+        }
+        // fold this group's factor into the channel PSDs
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-          const R tt = xr[b] + off;
-          E[g][b] = Math<R>::exp2_(a + tt * (bb + tt * (c + tt * d)));
+          if constexpr (MODE == kSplit) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) S[c][b] += Kt[g][c][b] * E[b];
+          } else if constexpr (MODE == kShared) {
+            // OMS and TM share the noise exponent; their amplitudes weight the rows
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+              S[c][b] += (g == 0 ? (w_oms * Kt[0][c][b] + w_tm * Kt[1][c][b]) : Kt[2][c][b]) * E[b];
+          } else {
+            if (g < 3) {
+              S[g][b] += (w_oms * Kt[0][g][b] + w_tm * Kt[1][g][b]) * E[b];
+            } else {
+#pragma unroll
+              for (int c = 0; c < NCH; ++c) S[c][b] += Kt[2][c][b] * E[b];
+            }
+          }
         }
-      } else {
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        // One reciprocal and one logarithm per bin for all channels:
+        //   sum_c ND_c / S_c = num / prod_c S_c,   sum_c w_c ln S_c = ln2 log2(prod_c S_c^w_c)
+        // (w = 2 for the merged A/E row).
+        R v;
+        if constexpr (NCH == 2) {
+          const R P = S[0][b] * S[1][b];
+          const R num = ND[1][b] * S[0][b] + ND[0][b] * S[1][b];
+          v = num * Math<R>::rcp_(P) + NL[b] * Math<R>::log2_(P * S[0][b]);
+        } else {
+          const R P01 = S[0][b] * S[1][b];
+          const R P = P01 * S[2][b];
+          const R num = S[2][b] * (ND[1][b] * S[0][b] + ND[0][b] * S[1][b]) + ND[2][b] * P01;
+          v = num * Math<R>::rcp_(P) + NL[b] * Math<R>::log2_(P);
+        }
+        acc += (double)v;
+      }
+      acc = wave_sum(acc);
+      if (!isfinite(acc)) {
+        // A channel product left the floating-point range (an extreme state):
+        // redo the chunk with one reciprocal and logarithm per channel, so that
+        // only a non-finite or vanishing channel PSD marks the state.
+        acc = 0.0;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-          const int k = min(kbase + b * kWave + lane, K - 1);
-          const double xk = x64[k];
-          int idx = i0;
-          for (int j = i0 + 1; j <= i1; ++j) idx += (bx[base + j] <= xk) ? 1 : 0;
-          const R* cf = coef + (base + idx) * 4;
-          const R tt = kMixed ? (R)(xk - bx[base + idx]) : (R)(xr[b] - bx[base + idx]);
-          E[g][b] = Math<R>::exp2_(cf[0] + tt * (cf[1] + tt * (cf[2] + tt * cf[3])));
+          R v = 0;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;
+            v += ND[c][b] * Math<R>::rcp_(S[c][b]) + (lw * NL[b]) * Math<R>::log2_(S[c][b]);
+          }
+          acc += (double)v;
         }
+        acc = wave_sum(acc);
       }
+      if (lane == 0) partial[(size_t)s * n_chunks + chunk] = acc;
     }
-    const StateScalars sc = scal[s];
-    const R w_oms = (R)sc.w_oms, w_tm = (R)sc.w_tm, e_fg = (R)sc.e_fg;
-    double acc = 0.0;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      R v = 0;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const R S = assemble<R, MODE, NCH, FG, B>(c, b, Kt, E, w_oms, w_tm, e_fg);
-        const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;   // A and E merged: ln S counted twice
-        v += ND[c][b] * Math<R>::rcp_(S) + (NL[b] * lw) * Math<R>::log2_(S);
-      }
-      acc += (double)v;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) partial[(size_t)s * n_chunks + chunk] = acc;
   }
 }
 

@@ -233,3 +233,27 @@ def test_repeatable_and_graph_replay(lps):
             # eager work between replays
             c = ctx.loglike_batch(st, prec)[0]
             assert torch.equal(c, a)
+
+
+def test_mixed_extreme_states_keep_fp64_status(lps):
+    """Spline heights far from zero push the per-bin product of channel PSDs out of
+    the single-precision range; the mixed path must still agree with FP64 on which
+    states are valid and on their logL (relative 1e-6)."""
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=2100, layout="split")
+    sb = W.make_states(name, ds, n_states=6, inbetween=(2, 6))
+    knots = [[(x.copy(), y.copy()) for (x, y) in C.knots_of(sb, s)] for s in range(sb.n)]
+    for s, shift in zip(range(sb.n), [14.0, -14.0, 20.0, -20.0, 0.0, 11.0]):
+        x, y = knots[s][0]
+        knots[s][0] = (x, y + shift)        # OMS spline shifted by `shift` dex
+    ext = W.pack_states(sb.params.copy(), knots, 3)
+    ctx = C.make_context(lps, ds, D, max_states=ext.n)
+    st = C.device_states(ctx, ext)
+    l64, s64 = ctx.loglike_batch(st, "fp64")
+    lmx, smx = ctx.loglike_batch(st, "mixed")
+    np.testing.assert_array_equal(s64.cpu().numpy(), smx.cpu().numpy())
+    a, b = l64.cpu().numpy(), lmx.cpu().numpy()
+    ok = np.isfinite(a)
+    assert np.all(np.abs(a[ok] - b[ok]) <= 1e-6 * np.abs(a[ok]))
+    ref = C.oracle_loglikes(ds, D, ext)
+    assert np.all(np.abs(a[ok] - ref[ok]) <= 1e-9 * np.abs(ref[ok]))
