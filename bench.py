@@ -142,7 +142,8 @@ def main():
     S0, _ = ctx0.psd_build(ctx0.states(ds.truth.params, ds.truth.knot_off, ds.truth.knot_x, ds.truth.knot_y))
     D = S0[0] * torch.as_tensor(ds.chi, device=dev)
     ctx0.close()
-    ctx = lps.Context(ds.f, ds.nk, D, ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=n, device=dev)
+    ctx = lps.Context(ds.f, ds.nk, D, ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=n, device=dev,
+                      max_grad_states=0)
     st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
     out = torch.empty(n, dtype=torch.float64, device=dev)
     status = torch.empty(n, dtype=torch.int32, device=dev)

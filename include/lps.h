@@ -55,7 +55,7 @@ typedef enum {
   LPS_OK = 0,
   LPS_E_NULL = 1,       /* a required pointer is NULL */
   LPS_E_SHAPE = 2,      /* a size or range argument is out of bounds */
-  LPS_E_CAPACITY = 3,   /* n_states > max_states, or k_max outside [2, 64] */
+  LPS_E_CAPACITY = 3,   /* n_states > max_states (max_grad_states for the gradient), or k_max outside [2, 64] */
   LPS_E_ROUTING = 4,    /* the routing table is not one the kernels implement */
   LPS_E_PRECISION = 5,  /* unknown precision enum */
   LPS_E_DEVICE = 6,     /* a HIP runtime call failed */
@@ -101,6 +101,9 @@ typedef struct {
                             route[LPS_TERM_FG][*] must be -1 */
   int32_t k_max;         /* max knots per spline including edges, 2..64 */
   int32_t max_states;    /* workspace capacity in states (>= 1) */
+  int32_t max_grad_states; /* states a gradient call may take (0..max_states; 0 = no
+                              gradient workspace).  The adjoint keeps per-chunk moment
+                              records: about 250 bytes per state per 128 bins. */
 } lps_dataset_desc;
 
 /* A batch of states: parameters plus ragged CSR knots (device arrays). */

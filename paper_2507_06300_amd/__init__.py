@@ -40,7 +40,8 @@ class _Desc(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("f", ctypes.c_void_p), ("nk", ctypes.c_void_p),
                 ("D", ctypes.c_void_p), ("R", ctypes.c_void_p), ("Rfg", ctypes.c_void_p),
                 ("f_knee", ctypes.c_double), ("arm_length", ctypes.c_double), ("n_spl", ctypes.c_int32),
-                ("route", ctypes.c_int8 * 12), ("k_max", ctypes.c_int32), ("max_states", ctypes.c_int32)]
+                ("route", ctypes.c_int8 * 12), ("k_max", ctypes.c_int32), ("max_states", ctypes.c_int32),
+                ("max_grad_states", ctypes.c_int32)]
 
 
 class _States(ctypes.Structure):
@@ -130,7 +131,7 @@ class Context:
     """One analysed dataset on one GPU (wraps lps_create / lps_destroy)."""
 
     def __init__(self, f, nk, D, R, route, n_spl, Rfg=None, k_max=64, max_states=1, f_knee=1.0e-3,
-                 arm_length=2.5e9, device=None):
+                 arm_length=2.5e9, device=None, max_grad_states=None):
         self.device = torch.device(device if device is not None else "cuda")
         dev = self.device
         self.f = _dev(f, torch.float64, dev)
@@ -154,6 +155,8 @@ class Context:
             d.route[i] = flat[i]
         d.k_max = int(k_max)
         d.max_states = self.max_states
+        self.max_grad_states = self.max_states if max_grad_states is None else int(max_grad_states)
+        d.max_grad_states = self.max_grad_states
         h = ctypes.c_void_p()
         idx = dev.index if dev.index is not None else torch.cuda.current_device()
         _check(lib().lps_create(ctypes.byref(d), idx, ctypes.byref(h)), "lps_create")

@@ -125,6 +125,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   if (!d->f || !d->nk || !d->D || !d->R) return LPS_E_NULL;
   if (d->n_bins < 1 || d->n_spl < 0 || d->n_spl > 4) return LPS_E_SHAPE;
   if (d->k_max < 2 || d->k_max > lps::kMaxKnots || d->max_states < 1) return LPS_E_CAPACITY;
+  if (d->max_grad_states < 0 || d->max_grad_states > d->max_states) return LPS_E_CAPACITY;
   if (!(d->f_knee > 0.0) || !(d->arm_length > 0.0)) return LPS_E_SHAPE;
   if (hipSetDevice(device) != hipSuccess) return LPS_E_DEVICE;
   const int K = d->n_bins;
@@ -162,6 +163,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   memcpy(c->route, d->route, sizeof(c->route));
   c->k_max = d->k_max;
   c->max_states = d->max_states;
+  c->max_grad_states = d->max_grad_states;
   c->f_knee = d->f_knee;
   c->arm_length = d->arm_length;
   c->lay = L;
@@ -192,7 +194,8 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
     c->gpartial_bytes = lps::grad_workspace_bytes(c);
     ok = hipMalloc((void**)&c->gpartial, c->gpartial_bytes) == hipSuccess;
   }
-  ok = ok && dalloc(&c->moments, S * (size_t)(d->n_spl > 0 ? d->n_spl : 1) * lps::kMaxKnots * 4) == hipSuccess;
+  ok = ok && dalloc(&c->moments, (size_t)(d->max_grad_states > 0 ? d->max_grad_states : 1) * G * lps::kMaxKnots * 4) ==
+                 hipSuccess;
   if (!ok) {
     free_ctx(c);
     return LPS_E_NOMEM;
@@ -260,6 +263,7 @@ lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st, lps_precis
   lps_status r = check_states(ctx, st);
   if (r != LPS_OK) return r;
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
+  if (st->n_states > ctx->max_grad_states) return LPS_E_CAPACITY;
   if (st->n_states == 0) return LPS_OK;
   if (!logL || !dparams) return LPS_E_NULL;
   if (ctx->n_spl > 0 && (!dknot_x || !dknot_y)) return LPS_E_NULL;

@@ -1,14 +1,648 @@
-// Adjoint of the batched forward pass (placeholder until the adjoint kernels land).
-#include "lps_internal.hpp"
+// Adjoint of the batched forward pass: logL and dlogL/d(theta) for every state.
+//
+// The score of the segment-averaged Whittle likelihood is
+//   dlogL/dS_ck = N_k (D_ck - S_ck) / S_ck^2
+// (from logL = -sum N_k (D/S + ln S)).  A PSD term tau enters S as
+// T_tau,c * 10^{P_j(x)} * amp_tau, so, with h_ck = dlogL/dS_ck,
+//   dlogL/d ln amp_tau   = sum_k sum_c h_ck T~_tau,ck
+//   dlogL/dP_j(x_k)      = ln 10 * sum over terms routed to spline j of h_ck T~_tau,ck
+// and the spline's knots enter through the per-piece moments
+//   M^p_i = sum_{k in piece i} dlogL/dP(x_k) (x_k - x_i)^p ,   p = 0..3,
+// followed by an O(n) backward through the Akima construction of App. A
+// (cubic coefficients -> knot slopes -> slope weights -> segment slopes ->
+// knots).  The power law of Eq. (pl) is part of the background group's
+// exponent, so dlogL/du and dlogL/dalpha follow from that group's moments.
+//
+// Three launches after the coefficient kernel:
+//   k_grad        per (chunk, state tile): logL partial, template sums and
+//                 first-piece moments per group in one 16/32-value record,
+//                 last-piece moments and interior pieces for chunks that
+//                 straddle a knot;
+//   k_grad_reduce per (state, group): stitches the chunk records into
+//                 per-piece moments in chunk order (deterministic);
+//   k_grad_finish per state: logL, template gradients, Akima backward.
+#include <math.h>
+
+#include "lps_batched.hpp"
+#include "lps_spline.hpp"
 
 namespace lps {
+namespace {
 
-size_t grad_workspace_bytes(const lps_ctx* ctx) { (void)ctx; return 256; }
+constexpr int kBGrad32 = 4;                       // bins per lane, mixed adjoint
+constexpr int kBGrad64 = 2;                       // bins per lane, FP64 adjoint
+constexpr int kChunkGrad32 = kWave * kBGrad32;    // 256
+constexpr int kChunkGrad64 = kWave * kBGrad64;    // 128
+
+template <int G>
+struct RecSize {
+  static constexpr int NVR = 4 + 4 * G;
+  static constexpr int M = NVR <= 16 ? 4 : 5;
+  static constexpr int NV = 1 << M;
+};
+
+// 64-lane reduce-scatter of NV = 2^M doubles: on return every lane holds the
+// full sum of value index (lane >> (6 - M)).  Fixed shuffle tree: deterministic.
+template <int M>
+__device__ inline double reduce_scatter(double (&v)[1 << M], int lane) {
+  constexpr int NV = 1 << M;
+#pragma unroll
+  for (int L = 0; L < M; ++L) {
+    const int half = NV >> (L + 1);
+    const bool hi = (lane >> (5 - L)) & 1;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double keep = hi ? v[half + i] : v[i];
+      const double send = hi ? v[i] : v[half + i];
+      v[i] = keep + __shfl_xor(send, 32 >> L, kWave);
+    }
+  }
+  double r = v[0];
+#pragma unroll
+  for (int off = (32 >> M); off >= 1; off >>= 1) r += __shfl_xor(r, off, kWave);
+  return r;
+}
+
+template <typename R, int MODE, int NCH, bool FG, int B>
+__global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_tiles, int tile, int K, int k_pad,
+                                              int ref_chunk, const R* __restrict__ tab,
+                                              const double* __restrict__ x64, const double* __restrict__ bx,
+                                              const R* __restrict__ coef, const int32_t* __restrict__ n_int,
+                                              const StateScalars* __restrict__ scal, double* __restrict__ rec,
+                                              int2* __restrict__ gidx, double* __restrict__ glast,
+                                              double* __restrict__ moments) {
+  constexpr int G = Groups<MODE>::G;
+  constexpr int NT = FG ? 4 : 3;
+  constexpr int CH = kWave * B;
+  constexpr int SUB = kWave / G;
+  constexpr int M = RecSize<G>::M;
+  constexpr int NV = RecSize<G>::NV;
+  constexpr bool kMixed = sizeof(R) == 4;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int item = blockIdx.x * kWavesPerBlock + uniform(threadIdx.x >> 6);
+  const int chunk = item % n_chunks;
+  const int t = item / n_chunks;
+  if (t >= n_tiles) return;
+  const int s_begin = t * tile;
+  const int s_end = min(s_begin + tile, n_states);
+  const int kbase = chunk * CH;
+
+  R xr[B], NL[B];
+  R Kt[NT][NCH][B];
+  R ND[NCH][B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int k = kbase + b * kWave + lane;
+    xr[b] = tab[k];
+#pragma unroll
+    for (int term = 0; term < NT; ++term)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) Kt[term][c][b] = tab[(size_t)tab_k(term, c, NCH) * k_pad + k];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) ND[c][b] = tab[(size_t)tab_nd(c, NT, NCH) * k_pad + k];
+    NL[b] = tab[(size_t)tab_nl(NT, NCH) * k_pad + k];
+  }
+  const int klast = min(kbase + CH, K) - 1;
+  const double xf = x64[kbase];
+  const double xl = x64[klast];
+  // abscissa origin of the single-precision table rows (start of their 512-bin block)
+  const double xo = kMixed ? x64[(kbase / ref_chunk) * ref_chunk] : 0.0;
+
+  for (int sub = s_begin; sub < s_end; sub += SUB) {
+    const int nsub = min(SUB, s_end - sub);
+    const int ps = lane / G, pg = lane - (lane / G) * G;
+    const bool pv = ps < nsub;
+    const size_t pbase = (size_t)((sub + ps) * G + pg) * kMaxKnots;
+    const int pni = pv ? n_int[(sub + ps) * G + pg] : 0;
+    int pi0 = 0, pi1 = 0;
+    R pa = 0, pb = 0, pc = 0, pd = 0, poff = 0;
+    if (pni > 0) {
+      pi0 = count_le(bx + pbase, pni, xf);
+      pi1 = count_le(bx + pbase, pni, xl);
+      const R* cf = coef + (pbase + pi0) * 4;
+      pa = cf[0];
+      pb = cf[1];
+      pc = cf[2];
+      pd = cf[3];
+      const double b0 = bx[pbase + pi0];
+      poff = kMixed ? (R)(xo - b0) : (R)(-b0);
+    }
+    R pw0 = 0, pw1 = 0, pw2 = 0;
+    if (pv && pg == 0) {
+      const StateScalars sc = scal[sub + ps];
+      pw0 = (R)sc.w_oms;
+      pw1 = (R)sc.w_tm;
+      pw2 = (R)sc.e_fg;
+    }
+
+    for (int q = 0; q < nsub; ++q) {
+      const int s = sub + q;
+      const size_t ro = (size_t)s * n_chunks + chunk;
+      if (__builtin_amdgcn_readlane(pni, q * G) == 0) {   // invalid state
+        if (lane < NV) rec[ro * NV + lane] = 0.0;
+        if (lane < G) gidx[ro * G + lane] = make_int2(0, 0);
+        continue;
+      }
+      const R w_oms = readlane_r(pw0, q * G), w_tm = readlane_r(pw1, q * G), e_fg = readlane_r(pw2, q * G);
+
+      // group factors E and piece abscissae T (t = x - x_piece) per bin
+      R E[G][B], T[G][B];
+      int gi0[G], gi1[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int pl = q * G + g;
+        const int i0 = __builtin_amdgcn_readlane(pi0, pl);
+        const int i1 = __builtin_amdgcn_readlane(pi1, pl);
+        gi0[g] = i0;
+        gi1[g] = i1;
+        if (i0 == i1) {
+          const R a = readlane_r(pa, pl), bb = readlane_r(pb, pl), cc = readlane_r(pc, pl),
+                  dd = readlane_r(pd, pl), off = readlane_r(poff, pl);
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            T[g][b] = xr[b] + off;
+            E[g][b] = Math<R>::exp2_(a + T[g][b] * (bb + T[g][b] * (cc + T[g][b] * dd)));
+          }
+        } else {
+          const size_t base = (size_t)(s * G + g) * kMaxKnots;
+          R Q[B];
+          for (int j = i0; j <= i1; ++j) {
+            const R* cf = coef + (base + j) * 4;
+            const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
+            const double bj = bx[base + j];
+            const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
+            const R lim = kMixed ? (R)(bj - xo) : (R)bj;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+              const R tt = xr[b] + off;
+              const R qv = a + tt * (bb + tt * (cc + tt * dd));
+              const bool sel = (j == i0) || (xr[b] >= lim);
+              Q[b] = sel ? qv : Q[b];
+              T[g][b] = sel ? tt : T[g][b];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < B; ++b) E[g][b] = Math<R>::exp2_(Q[b]);
+        }
+      }
+
+      // channel PSDs, score, per-group sensitivities and first-piece moments
+      double vals[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) vals[i] = 0.0;
+      R gq_keep[G][B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        R S[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) S[c] = FG ? Kt[3][c][b] * e_fg : (R)0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if constexpr (MODE == kSplit) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) S[c] += Kt[g][c][b] * E[g][b];
+          } else if constexpr (MODE == kShared) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+              S[c] += (g == 0 ? (w_oms * Kt[0][c][b] + w_tm * Kt[1][c][b]) : Kt[2][c][b]) * E[g][b];
+          } else {
+            if (g < 3) {
+              S[g] += (w_oms * Kt[0][g][b] + w_tm * Kt[1][g][b]) * E[g][b];
+            } else {
+#pragma unroll
+              for (int c = 0; c < NCH; ++c) S[c] += Kt[2][c][b] * E[g][b];
+            }
+          }
+        }
+        const R Nn = NL[b] * (R)(1.0 / kLn2);
+        R h[NCH];
+        R lsum = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;
+          const R r = Math<R>::rcp_(S[c]);
+          const R q1 = ND[c][b] * r;
+          lsum += q1 + (lw * NL[b]) * Math<R>::log2_(S[c]);
+          h[c] = (q1 - lw * Nn) * r;       // dlogL/dS~ (scaled units), A and E summed when merged
+        }
+        vals[0] += (double)lsum;
+        R fg_sum = 0;
+        if constexpr (FG) {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) fg_sum += h[c] * Kt[3][c][b];
+          vals[3] += (double)(fg_sum * e_fg);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          R gq;
+          if constexpr (MODE == kSplit) {
+            R a = 0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) a += h[c] * Kt[g][c][b];
+            gq = a * E[g][b];
+          } else {
+            const bool noise = MODE == kShared ? g == 0 : g < 3;
+            if (noise) {
+              R ao = 0, at = 0;
+              if constexpr (MODE == kShared) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                  ao += h[c] * Kt[0][c][b];
+                  at += h[c] * Kt[1][c][b];
+                }
+              } else {
+                ao = h[g] * Kt[0][g][b];
+                at = h[g] * Kt[1][g][b];
+              }
+              const R ro_ = w_oms * ao * E[g][b], rt_ = w_tm * at * E[g][b];
+              vals[1] += (double)ro_;
+              vals[2] += (double)rt_;
+              gq = ro_ + rt_;
+            } else {
+              R a = 0;
+#pragma unroll
+              for (int c = 0; c < NCH; ++c) a += h[c] * Kt[2][c][b];
+              gq = a * E[g][b];
+            }
+          }
+          gq_keep[g][b] = gq;
+        }
+      }
+      // moments of the first piece: bins whose piece index equals i0
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int i0 = gi0[g], i1 = gi1[g];
+        R lim1 = 0;
+        if (i1 > i0) {
+          const double b1 = bx[(size_t)(s * G + g) * kMaxKnots + i0 + 1];
+          lim1 = kMixed ? (R)(b1 - xo) : (R)b1;
+        }
+        R m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const bool in0 = (i1 == i0) || (xr[b] < lim1);
+          const R gq = in0 ? gq_keep[g][b] : (R)0;
+          const R tt = T[g][b];
+          const R u1 = gq * tt, u2 = u1 * tt;
+          m0 += gq;
+          m1 += u1;
+          m2 += u2;
+          m3 += u2 * tt;
+        }
+        vals[4 + 4 * g + 0] += (double)m0;
+        vals[4 + 4 * g + 1] += (double)m1;
+        vals[4 + 4 * g + 2] += (double)m2;
+        vals[4 + 4 * g + 3] += (double)m3;
+      }
+      const double red = reduce_scatter<M>(vals, lane);
+      if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = red;
+      if (lane < G) {
+        int a0 = 0, a1 = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (lane == g) {
+            a0 = gi0[g];
+            a1 = gi1[g];
+          }
+        gidx[ro * G + lane] = make_int2(a0, a1);
+      }
+      // later pieces of chunks that straddle knots (rare): interior pieces are
+      // complete here and go straight to the moment table; the last piece is
+      // stitched with the next chunk by the reducer
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int i0 = gi0[g], i1 = gi1[g];
+        if (i1 == i0) continue;
+        const size_t base = (size_t)(s * G + g) * kMaxKnots;
+        for (int j = i0 + 1; j <= i1; ++j) {
+          const double bj = bx[base + j];
+          const R lo = kMixed ? (R)(bj - xo) : (R)bj;
+          R hi = 0;
+          if (j < i1) {
+            const double bj1 = bx[base + j + 1];
+            hi = kMixed ? (R)(bj1 - xo) : (R)bj1;
+          }
+          double mm[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            const bool in = (xr[b] >= lo) && (j == i1 || xr[b] < hi);
+            const R gq = in ? gq_keep[g][b] : (R)0;
+            const R tt = T[g][b];
+            const R u1 = gq * tt, u2 = u1 * tt;
+            mm[0] += (double)gq;
+            mm[1] += (double)u1;
+            mm[2] += (double)u2;
+            mm[3] += (double)(u2 * tt);
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p) mm[p] = wave_sum(mm[p]);
+          if (lane == 0) {
+            double* dst = (j == i1) ? glast + (ro * G + g) * 4 : moments + ((size_t)(s * G + g) * kMaxKnots + j) * 4;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) dst[p] = mm[p];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Stitch chunk records into per-piece moments, in chunk order.
+__global__ void k_grad_reduce(int n_states, int G, int NV, int n_chunks, const int32_t* __restrict__ n_int,
+                              const double* __restrict__ rec, const int2* __restrict__ gidx,
+                              const double* __restrict__ glast, double* __restrict__ moments) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n_states * G) return;
+  const int s = id / G, g = id - (id / G) * G;
+  const int n = n_int[s * G + g];
+  if (n == 0) return;
+  double* mo = moments + (size_t)(s * G + g) * kMaxKnots * 4;
+  int cur = 0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < n_chunks; ++c) {
+    const size_t ro = (size_t)s * n_chunks + c;
+    const int2 ab = gidx[ro * G + g];
+    const double* first = rec + ro * NV + 4 + 4 * g;
+    if (ab.x > cur) {
+      for (int p = 0; p < 4; ++p) mo[cur * 4 + p] = acc[p];
+      for (int j = cur + 1; j < ab.x; ++j)
+        for (int p = 0; p < 4; ++p) mo[j * 4 + p] = 0.0;   // no bin falls in piece j
+      cur = ab.x;
+      for (int p = 0; p < 4; ++p) acc[p] = 0.0;
+    }
+    for (int p = 0; p < 4; ++p) acc[p] += first[p];
+    if (ab.y > ab.x) {
+      for (int p = 0; p < 4; ++p) mo[cur * 4 + p] = acc[p];
+      cur = ab.y;
+      const double* last = glast + (ro * G + g) * 4;
+      for (int p = 0; p < 4; ++p) acc[p] = last[p];
+    }
+  }
+  for (int p = 0; p < 4; ++p) mo[cur * 4 + p] = acc[p];
+  for (int j = cur + 1; j < n; ++j)
+    for (int p = 0; p < 4; ++p) mo[j * 4 + p] = 0.0;
+}
+
+// Backward through the spline construction of App. A for one spline:
+// given Mbar[i][p] (moments of dlogL/dP over piece i, already times ln 10)
+// accumulate dlogL/dy_i and dlogL/dx_i (edges excluded).
+__device__ void spline_backward(const double* __restrict__ x, const double* __restrict__ y, int n,
+                                const double* __restrict__ mom, double* __restrict__ dy, double* __restrict__ dx) {
+  double m[kMaxKnots], h[kMaxKnots], s[kMaxKnots], w[kMaxKnots];
+  double mb[kMaxKnots], hb[kMaxKnots], sb[kMaxKnots], wb[kMaxKnots], yb[kMaxKnots], xb[kMaxKnots];
+  for (int i = 0; i < n; ++i) {
+    yb[i] = 0.0;
+    xb[i] = 0.0;
+    sb[i] = 0.0;
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    h[i] = x[i + 1] - x[i];
+    m[i] = (y[i + 1] - y[i]) / h[i];
+    mb[i] = 0.0;
+    hb[i] = 0.0;
+  }
+  const bool akima = n >= 4;
+  if (akima) {
+    for (int i = 0; i + 2 < n; ++i) {
+      w[i] = fabs(m[i + 1] - m[i]);
+      wb[i] = 0.0;
+    }
+    s[0] = 0.5 * (3.0 * m[0] - m[1]);
+    s[n - 1] = 0.5 * (3.0 * m[n - 2] - m[n - 3]);
+    for (int i = 1; i <= n - 2; ++i) {
+      const int ir = i < n - 2 ? i : n - 3;
+      const int il = i - 2 > 0 ? i - 2 : 0;
+      s[i] = akima_avg(w[ir], m[i - 1], w[il], m[i]);
+    }
+  } else {
+    for (int i = 0; i + 1 < n; ++i) s[i] = m[i];
+  }
+  // pieces: a = y_i, b = s_i (or m_i), c, d; P = a + b t + c t^2 + d t^3, t = x - x_i
+  for (int i = 0; i + 1 < n; ++i) {
+    const double M0 = mom[i * 4 + 0], M1 = mom[i * 4 + 1], M2 = mom[i * 4 + 2], M3 = mom[i * 4 + 3];
+    if (akima) {
+      const double hi = h[i];
+      const double c = (3.0 * m[i] - 2.0 * s[i] - s[i + 1]) / hi;
+      const double d = (s[i] + s[i + 1] - 2.0 * m[i]) / (hi * hi);
+      yb[i] += M0;
+      sb[i] += M1;
+      xb[i] -= s[i] * M0 + 2.0 * c * M1 + 3.0 * d * M2;      // t depends on x_i
+      // c = (3 m - 2 s_i - s_{i+1}) / h
+      mb[i] += 3.0 * M2 / hi;
+      sb[i] -= 2.0 * M2 / hi;
+      sb[i + 1] -= M2 / hi;
+      hb[i] -= M2 * c / hi;
+      // d = (s_i + s_{i+1} - 2 m) / h^2
+      const double h2 = hi * hi;
+      sb[i] += M3 / h2;
+      sb[i + 1] += M3 / h2;
+      mb[i] -= 2.0 * M3 / h2;
+      hb[i] -= 2.0 * M3 * d / hi;
+    } else {
+      yb[i] += M0;
+      mb[i] += M1;
+      xb[i] -= m[i] * M0;
+    }
+  }
+  if (akima) {
+    // knot slopes
+    mb[0] += 1.5 * sb[0];
+    mb[1] -= 0.5 * sb[0];
+    mb[n - 2] += 1.5 * sb[n - 1];
+    mb[n - 3] -= 0.5 * sb[n - 1];
+    for (int i = 1; i <= n - 2; ++i) {
+      const int ir = i < n - 2 ? i : n - 3;
+      const int il = i - 2 > 0 ? i - 2 : 0;
+      const double wr = w[ir], wl = w[il], den = wr + wl;
+      if (den == 0.0) {
+        mb[i - 1] += 0.5 * sb[i];
+        mb[i] += 0.5 * sb[i];
+      } else {
+        mb[i - 1] += sb[i] * wr / den;
+        mb[i] += sb[i] * wl / den;
+        wb[ir] += sb[i] * (m[i - 1] - s[i]) / den;
+        wb[il] += sb[i] * (m[i] - s[i]) / den;
+      }
+    }
+    // slope weights w_i = |m_{i+1} - m_i| (derivative 0 at 0)
+    for (int i = 0; i + 2 < n; ++i) {
+      const double dlt = m[i + 1] - m[i];
+      const double sg = dlt > 0.0 ? 1.0 : (dlt < 0.0 ? -1.0 : 0.0);
+      mb[i + 1] += wb[i] * sg;
+      mb[i] -= wb[i] * sg;
+    }
+  }
+  // segment slopes m_i = (y_{i+1} - y_i) / h_i
+  for (int i = 0; i + 1 < n; ++i) {
+    yb[i + 1] += mb[i] / h[i];
+    yb[i] -= mb[i] / h[i];
+    hb[i] -= mb[i] * m[i] / h[i];
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    xb[i + 1] += hb[i];
+    xb[i] -= hb[i];
+  }
+  for (int i = 0; i < n; ++i) {
+    dy[i] = yb[i];
+    dx[i] = (i == 0 || i == n - 1) ? 0.0 : xb[i];
+  }
+}
+
+__global__ void k_grad_finish(int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay,
+                              double x_knee, const double* __restrict__ params, const int32_t* __restrict__ off,
+                              const double* __restrict__ kx, const double* __restrict__ ky,
+                              const int32_t* __restrict__ n_int, const double* __restrict__ bx,
+                              const double* __restrict__ rec, const double* __restrict__ moments,
+                              const double* __restrict__ c0, const uint32_t* __restrict__ status_ws,
+                              double* __restrict__ logL, double* __restrict__ dparams, double* __restrict__ dkx,
+                              double* __restrict__ dky, uint32_t* __restrict__ status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_states) return;
+  const int G = lay.n_grp;
+  uint32_t st = status_ws[s];
+  double sums[4] = {0.0, 0.0, 0.0, 0.0};
+  if (st == 0) {
+    for (int c = 0; c < n_chunks; ++c) {
+      const double* r = rec + ((size_t)s * n_chunks + c) * NV;
+      for (int i = 0; i < 4; ++i) sums[i] += r[i];
+    }
+  }
+  const double L = c0[0] - sums[0];
+  if (st == 0 && !isfinite(L)) st |= LPS_ST_PSD;
+  if (status) status[s] = st;
+  if (st) {
+    logL[s] = -INFINITY;
+    for (int p = 0; p < n_params; ++p) dparams[p * (size_t)n_states + s] = 0.0;
+    for (int j = 0; j < n_spl; ++j) {
+      const int a = off[s * n_spl + j], b = off[s * n_spl + j + 1];
+      for (int i = a; a >= 0 && i < b; ++i) {
+        dkx[i] = 0.0;
+        dky[i] = 0.0;
+      }
+    }
+    return;
+  }
+  logL[s] = L;
+  const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
+  const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
+  double r_oms = sums[1], r_tm = sums[2];
+  double du = 0.0, dalpha = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const int ni = n_int[s * G + g];
+    const double* mo = moments + (size_t)(s * G + g) * kMaxKnots * 4;
+    const double* bxs = bx + (size_t)(s * G + g) * kMaxKnots;
+    double m0 = 0.0, m1x = 0.0;
+    for (int i = 0; i < ni; ++i) {
+      m0 += mo[i * 4 + 0];
+      m1x += mo[i * 4 + 1] + (bxs[i] - x_knee) * mo[i * 4 + 0];
+    }
+    switch (lay.grp_kind[g]) {
+      case kGOms: r_oms = m0; break;
+      case kGTm: r_tm = m0; break;
+      case kGSgwb:
+        du = kLn10 * m0;
+        dalpha = kLn10 * m1x;
+        break;
+      default: break;
+    }
+  }
+  dparams[LPS_P_AOMS * (size_t)n_states + s] = 2.0 * r_oms / a_oms;
+  dparams[LPS_P_ATM * (size_t)n_states + s] = 2.0 * r_tm / a_tm;
+  dparams[LPS_P_U * (size_t)n_states + s] = du;
+  dparams[LPS_P_ALPHA * (size_t)n_states + s] = dalpha;
+  if (n_params > 4) dparams[LPS_P_UFG * (size_t)n_states + s] = kLn10 * sums[3];
+  // spline knots: sum the moments of every group fed by the spline
+  double mom[kMaxKnots * 4];
+  for (int j = 0; j < n_spl; ++j) {
+    const int a = off[s * n_spl + j];
+    const int n = off[s * n_spl + j + 1] - a;
+    if (n == 0) continue;
+    for (int i = 0; i < (n - 1) * 4; ++i) mom[i] = 0.0;
+    for (int g = 0; g < G; ++g) {
+      if (lay.grp_spline[g] != j) continue;
+      const double* mo = moments + (size_t)(s * G + g) * kMaxKnots * 4;
+      for (int i = 0; i < (n - 1) * 4; ++i) mom[i] += kLn10 * mo[i];
+    }
+    spline_backward(kx + a, ky + a, n, mom, dky + a, dkx + a);
+  }
+}
+
+template <typename R, int B>
+hipError_t dispatch_grad(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, const R* tab, const R* coef,
+                         int NV, double* rec, int2* gidx, double* glast, hipStream_t s) {
+  const Layout& L = ctx->lay;
+  const int items = n_chunks * n_tiles;
+  dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
+  const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
+#define LPS_GRAD(MODE, NCH, FG)                                                                            \
+  hipLaunchKernelGGL((k_grad<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,       \
+                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->n_int, ctx->scal, rec, \
+                     gidx, glast, ctx->moments)
+  const bool fg = L.has_fg != 0;
+  if (L.mode == kSplit && L.nch == 2 && !fg) LPS_GRAD(kSplit, 2, false);
+  else if (L.mode == kSplit && L.nch == 2 && fg) LPS_GRAD(kSplit, 2, true);
+  else if (L.mode == kSplit && L.nch == 3 && !fg) LPS_GRAD(kSplit, 3, false);
+  else if (L.mode == kSplit && L.nch == 3 && fg) LPS_GRAD(kSplit, 3, true);
+  else if (L.mode == kShared && L.nch == 2 && !fg) LPS_GRAD(kShared, 2, false);
+  else if (L.mode == kShared && L.nch == 2 && fg) LPS_GRAD(kShared, 2, true);
+  else if (L.mode == kShared && L.nch == 3 && !fg) LPS_GRAD(kShared, 3, false);
+  else if (L.mode == kShared && L.nch == 3 && fg) LPS_GRAD(kShared, 3, true);
+  else if (L.mode == kPaper && !fg) LPS_GRAD(kPaper, 3, false);
+  else LPS_GRAD(kPaper, 3, true);
+#undef LPS_GRAD
+  return hipGetLastError();
+}
+
+int grad_nv(const Layout& L) {
+  const int nvr = 4 + 4 * L.n_grp;
+  return nvr <= 16 ? 16 : 32;
+}
+
+}  // namespace
+
+size_t grad_workspace_bytes(const lps_ctx* ctx) {
+  const size_t S = (size_t)ctx->max_grad_states;
+  if (S == 0) return 256;
+  const size_t nch = (size_t)((ctx->n_bins + kChunkGrad64 - 1) / kChunkGrad64);
+  const size_t G = (size_t)ctx->lay.n_grp;
+  const size_t nv = (size_t)grad_nv(ctx->lay);
+  return S * nch * (nv * 8 + G * 8 + G * 4 * 8) + 256;
+}
 
 hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL, double* dparams,
                        double* dkx, double* dky, uint32_t* status, hipStream_t s) {
-  (void)ctx; (void)st; (void)prec; (void)logL; (void)dparams; (void)dkx; (void)dky; (void)status; (void)s;
-  return hipErrorNotSupported;
+  const int n = st->n_states;
+  hipError_t e = launch_coeffs(ctx, st, s);
+  if (e != hipSuccess) return e;
+  const bool mixed = prec == LPS_MIXED;
+  const int chunk = mixed ? kChunkGrad32 : kChunkGrad64;
+  const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
+  const int G = ctx->lay.n_grp;
+  const int NV = grad_nv(ctx->lay);
+  double* rec = ctx->gpartial;
+  int2* gidx = (int2*)(rec + (size_t)n * n_chunks * NV);
+  double* glast = (double*)(gidx + (size_t)n * n_chunks * G);
+  long target = 8192;
+  long tile = ((long)n * n_chunks) / target;
+  if (tile < 1) tile = 1;
+  if (tile > 64) tile = 64;
+  if (tile > n) tile = n;
+  const int n_tiles = (n + (int)tile - 1) / (int)tile;
+  timing_begin(ctx, s);
+  if (mixed)
+    e = dispatch_grad<float, kBGrad32>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab32, ctx->coef32, NV, rec, gidx,
+                                       glast, s);
+  else
+    e = dispatch_grad<double, kBGrad64>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab64, ctx->coef64, NV, rec,
+                                        gidx, glast, s);
+  if (e != hipSuccess) return e;
+  timing_end(ctx, s);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((n * G + 127) / 128), dim3(128), 0, s, n, G, NV, n_chunks, ctx->n_int, rec,
+                     gidx, glast, ctx->moments);
+  hipLaunchKernelGGL(k_grad_finish, dim3((n + 63) / 64), dim3(64), 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
+                     ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_x, st->knot_y, ctx->n_int,
+                     ctx->bx, rec, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams, dkx, dky, status);
+  return hipGetLastError();
 }
 
 }  // namespace lps

@@ -90,6 +90,7 @@ struct lps_ctx {
   int8_t route[4][3];
   int32_t k_max;
   int32_t max_states;
+  int32_t max_grad_states;
   double f_knee;
   double arm_length;
   double x_first, x_last;   // log10 of the first and last bin (coverage test)
@@ -118,7 +119,7 @@ struct lps_ctx {
   double* partial;     // [max_states][max(n_chunks64, n_chunks32)]
   double* gpartial;    // gradient workspace (see lps_grad.hip)
   size_t gpartial_bytes;
-  double* moments;     // [max_states][n_spl][kMaxKnots][4]
+  double* moments;     // [max_grad_states][n_grp][kMaxKnots][4] per-piece adjoint moments
   double* plain_part;  // [max_states][plain blocks]
   int32_t plain_blocks;
   uint32_t* sticky;    // [1] device error flags

@@ -1,0 +1,149 @@
+"""GPU parity of the adjoint: dlogL/d(params, knot heights, knot positions) vs the FP64 oracle.
+
+FP64 adjoint: |dg| <= 1e-8 * (||g_family||_inf + tiny) per family (params, heights, positions)
+mixed adjoint: |dg| <= 2e-4 * ||g_family||_inf (single-precision per-bin scores and moments)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from oracle import lps_oracle as O  # noqa: E402
+from synth import workloads as W  # noqa: E402
+from tests import cases as C  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_06300_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+GRAD_CASES = [
+    ("grad_25000bins_1024states", "split", 1777, 9, (0, 10)),
+    ("avg50_1000bins_64states", "noise_signal", 1000, 6, (4, 4)),
+    ("grad_25000bins_1024states", "paper", 1303, 6, (0, 8)),
+    ("sweep_250000bins_2048chains", "split_fg", 2049, 6, (0, 14)),
+]
+
+
+def _oracle_grads(ds, D, sb):
+    out = []
+    for s in range(sb.n):
+        out.append(O.loglike_grad(ds, D, sb.params[:, s], C.knots_of(sb, s)))
+    return out
+
+
+def _unpack(sb, dkx, dky):
+    """CSR gradients -> per (state, spline) arrays."""
+    res = []
+    for s in range(sb.n):
+        row = []
+        for j in range(sb.n_spl):
+            a, b = int(sb.knot_off[s * sb.n_spl + j]), int(sb.knot_off[s * sb.n_spl + j + 1])
+            row.append((dky[a:b], dkx[a:b]))
+        res.append(row)
+    return res
+
+
+def _compare(sb, ref, logL, dp, dkx, dky, rel, label):
+    dp = dp.cpu().numpy()
+    per = _unpack(sb, dkx.cpu().numpy(), dky.cpu().numpy())
+    worst = 0.0
+    for s in range(sb.n):
+        rl, rdp, rdy, rdx = ref[s]
+        assert abs(logL[s] - rl) <= (1e-9 if rel < 1e-6 else 1e-6) * abs(rl)
+        # template parameters: compare the dimensionless sensitivities theta * dlogL/dtheta
+        scale = np.array([sb.params[0, s], sb.params[1, s], 1.0, 1.0, 1.0][:dp.shape[0]])
+        a, b = dp[:, s] * scale, rdp * scale
+        tol = rel * (np.abs(b).max() + 1.0)
+        worst = max(worst, np.abs(a - b).max() / tol)
+        assert np.all(np.abs(a - b) <= tol), (label, "params", s, a, b)
+        gy = np.concatenate([per[s][j][0] for j in range(sb.n_spl)])
+        ry = np.concatenate(rdy)
+        gx = np.concatenate([per[s][j][1] for j in range(sb.n_spl)])
+        rx = np.concatenate(rdx)
+        if ry.size:
+            tol = rel * (np.abs(ry).max() + 1.0)
+            worst = max(worst, np.abs(gy - ry).max() / tol)
+            assert np.all(np.abs(gy - ry) <= tol), (label, "heights", s)
+            tol = rel * (np.abs(rx).max() + 1.0)
+            worst = max(worst, np.abs(gx - rx).max() / tol)
+            assert np.all(np.abs(gx - rx) <= tol), (label, "positions", s, np.abs(gx - rx).max(), tol)
+    _say(label, "worst error / tolerance", worst)
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[c[1] for c in GRAD_CASES])
+def test_gradient_matches_oracle(lps, case):
+    name, layout, n_bins, n_states, inb = case
+    _say("grad case", case)
+    ds, D = C.dataset_with_data(name, n_bins=n_bins, layout=layout)
+    sb = W.make_states(name, ds, n_states=n_states, inbetween=inb)
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    ref = _oracle_grads(ds, D, sb)
+    logL, dp, dkx, dky, status = ctx.loglike_grad_batch(st, "fp64")
+    assert np.all(status.cpu().numpy() == 0)
+    _compare(sb, ref, logL.cpu().numpy(), dp, dkx, dky, 1e-8, "fp64")
+    f64 = ctx.loglike_batch(st, "fp64")[0].cpu().numpy()
+    assert np.all(np.abs(logL.cpu().numpy() - f64) <= 1e-12 * np.abs(f64))
+    logL, dp, dkx, dky, status = ctx.loglike_grad_batch(st, "mixed")
+    assert np.all(status.cpu().numpy() == 0)
+    _compare(sb, ref, logL.cpu().numpy(), dp, dkx, dky, 2e-4, "mixed")
+
+
+def test_gradient_invalid_states_and_determinism(lps):
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=900, layout="split")
+    sb = W.make_states(name, ds, n_states=5, inbetween=(2, 6))
+    knots = [[(x.copy(), y.copy()) for (x, y) in C.knots_of(sb, s)] for s in range(sb.n)]
+    x0, y0 = knots[1][0]
+    knots[1][0] = (x0[::-1].copy(), y0)
+    bad = W.pack_states(sb.params.copy(), knots, 3)
+    ctx = C.make_context(lps, ds, D, max_states=bad.n)
+    st = C.device_states(ctx, bad)
+    for prec in ("fp64", "mixed"):
+        a = ctx.loglike_grad_batch(st, prec)
+        b = ctx.loglike_grad_batch(st, prec)
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
+        logL, dp, dkx, dky, status = a
+        ref_status = C.oracle_status(ds, bad)
+        np.testing.assert_array_equal(status.cpu().numpy(), ref_status)
+        assert ref_status[1] & O.ST_ORDER
+        assert np.isneginf(logL[1].item())
+        assert torch.all(dp[:, 1] == 0)
+        lo, hi = int(bad.knot_off[3]), int(bad.knot_off[6])
+        assert torch.all(dkx[lo:hi] == 0) and torch.all(dky[lo:hi] == 0)
+
+
+def test_autograd_function(lps):
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=700, layout="split")
+    sb = W.make_states(name, ds, n_states=4, inbetween=(2, 5))
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    params = st.params.clone().requires_grad_(True)
+    kx = st.knot_x.clone().requires_grad_(True)
+    ky = st.knot_y.clone().requires_grad_(True)
+    logL = lps.LogLikeFn.apply(ctx, "fp64", params, kx, ky, st.knot_off)
+    w = torch.tensor([1.0, -2.0, 0.5, 3.0], dtype=torch.float64, device=logL.device)
+    (logL * w).sum().backward()
+    _, dp, dkx, dky, _ = ctx.loglike_grad_batch(st, "fp64")
+    assert torch.allclose(params.grad, dp * w[None, :], rtol=1e-12, atol=0)
+    off = sb.knot_off
+    owner = np.repeat(np.arange(sb.n), np.diff(off[::sb.n_spl]))
+    wk = w.cpu().numpy()[owner]
+    np.testing.assert_allclose(kx.grad.cpu().numpy(), dkx.cpu().numpy() * wk, rtol=1e-12)
+    np.testing.assert_allclose(ky.grad.cpu().numpy(), dky.cpu().numpy() * wk, rtol=1e-12)
