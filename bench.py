@@ -69,11 +69,29 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--grad-workload", default="grad_25000bins_1024states")
+    p.add_argument("--copy-check", action="store_true",
+                   help="also run one 1 GiB device-to-device copy (HBM counter calibration)")
+    p.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
     return p.parse_args()
+
+
+EAGER = False
 
 
 def timed_graph(torch, fn, steps, warmup):
     """Capture fn() into a graph, replay warmup + steps times; returns seconds for `steps`."""
+    if EAGER:
+        for _ in range(max(1, warmup)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, None
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -119,6 +137,8 @@ def cpu_baseline(name, n_states, dataset_bins=None):
 
 def main():
     args = parse()
+    global EAGER
+    EAGER = args.eager
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by walker; see the design notes)", file=sys.stderr)
@@ -147,6 +167,20 @@ def main():
     st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
     out = torch.empty(n, dtype=torch.float64, device=dev)
     status = torch.empty(n, dtype=torch.int32, device=dev)
+
+    if args.copy_check:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # --- autotune the launch shape of each precision on this batch --------------
+    shapes = {}
+    for prec in ("mixed", "fp64"):
+        ms, shp = ctx.autotune(st, prec, reps=3)
+        shapes[prec] = {"bins_per_lane": shp[0], "states_per_tile": shp[1], "autotune_ms": ms}
+        log(f"autotune {prec}: bins/lane {shp[0]}, states/tile {shp[1]} ({ms:.3f} ms)")
 
     # --- headline: mixed batched, graph-replayed -------------------------------
     log("mixed batched ...")
@@ -205,6 +239,7 @@ def main():
                          "precision": "mixed"},
               "roofline": roofline,
               "fp64_batched": {"value": fp64_value, "unit": UNIT, "ms_per_call": t64 / steps64 * 1e3},
+              "launch_shapes": shapes,
               "mixed_error": mixed_err}
 
     # --- plain FP64 per-state path on a state sample ---------------------------

@@ -173,6 +173,28 @@ lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st /*[host]*/,
                                   uint32_t* status, void* stream);
 
 /*
+ * Launch shape of the batched forward kernel for one precision: bins per lane
+ * (the wave's chunk is 64 times that; mixed: 4 or 8, FP64: 2 or 4) and states
+ * per work item (1..4096).  0 selects the built-in default (mixed 8, FP64 4;
+ * states sized so that about 8192 wave work items are launched).
+ */
+lps_status lps_set_launch(lps_ctx* ctx, lps_precision prec, int32_t bins_per_lane, int32_t states_per_tile);
+
+/* The launch shape a call with n_states states would use [host outputs]. */
+lps_status lps_get_launch(lps_ctx* ctx, lps_precision prec, int32_t n_states, int32_t* bins_per_lane /*[host]*/,
+                          int32_t* states_per_tile /*[host]*/);
+
+/*
+ * Autotuner: times every candidate launch shape of the forward kernel on the
+ * given batch (reps timed calls each, HIP events on `stream`), keeps the
+ * fastest for this precision and reports its milliseconds per call in
+ * *best_ms [host].  A setup call: it allocates a scratch output and
+ * synchronises; do not call it while capturing a graph.
+ */
+lps_status lps_autotune(lps_ctx* ctx, const lps_states* st /*[host]*/, lps_precision prec, int32_t reps,
+                        double* best_ms /*[host]*/, void* stream);
+
+/*
  * Per-kernel timing: when enabled, the forward and gradient entry points
  * record HIP events around their main kernel on the call's stream.
  * lps_kernel_time_ms synchronises and returns the summed milliseconds and

@@ -51,7 +51,7 @@ class _States(ctypes.Structure):
 
 SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
            "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error", "lps_strerror",
-           "lps_chunk_bins", "lps_valu_probe"]
+           "lps_chunk_bins", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune"]
 
 _lib = None
 
@@ -79,8 +79,15 @@ def lib():
     L.lps_chunk_bins.argtypes = [ctypes.c_int]
     L.lps_chunk_bins.restype = ctypes.c_int32
     dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
     L.lps_valu_probe.argtypes = [ctypes.c_int, dp, dp, dp]
     L.lps_valu_probe.restype = st
+    L.lps_set_launch.argtypes = [vp, ctypes.c_int, i32, i32]
+    L.lps_set_launch.restype = st
+    L.lps_get_launch.argtypes = [vp, ctypes.c_int, i32, ip, ip]
+    L.lps_get_launch.restype = st
+    L.lps_autotune.argtypes = [vp, ctypes.POINTER(_States), ctypes.c_int, i32, dp, vp]
+    L.lps_autotune.restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
         getattr(L, name).restype = st
@@ -221,6 +228,24 @@ class Context:
         _check(lib().lps_loglike_plain_fp64(self._h, ctypes.byref(c), _ptr(logL), _ptr(status), _stream(stream)),
                "lps_loglike_plain_fp64")
         return logL, status
+
+    def set_launch(self, precision, bins_per_lane=0, states_per_tile=0):
+        _check(lib().lps_set_launch(self._h, _PREC.get(precision, precision), int(bins_per_lane),
+                                    int(states_per_tile)), "lps_set_launch")
+
+    def get_launch(self, precision, n_states):
+        b, t = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lps_get_launch(self._h, _PREC.get(precision, precision), int(n_states), ctypes.byref(b),
+                                    ctypes.byref(t)), "lps_get_launch")
+        return b.value, t.value
+
+    def autotune(self, st: States, precision="mixed", reps=3, stream=None):
+        """Time the candidate launch shapes on this batch and keep the fastest."""
+        ms = ctypes.c_double()
+        c = st._c()
+        _check(lib().lps_autotune(self._h, ctypes.byref(c), _PREC.get(precision, precision), int(reps),
+                                  ctypes.byref(ms), _stream(stream)), "lps_autotune")
+        return ms.value, self.get_launch(precision, st.n)
 
     def set_timing(self, on: bool):
         _check(lib().lps_set_timing(self._h, 1 if on else 0), "lps_set_timing")

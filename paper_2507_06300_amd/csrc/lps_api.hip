@@ -171,7 +171,8 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
 
   const size_t S = (size_t)d->max_states;
   const size_t G = (size_t)L.n_grp;
-  const size_t nchunk = (size_t)(c->n_chunks64 > c->n_chunks32 ? c->n_chunks64 : c->n_chunks32);
+  // partial sums per (state, chunk) for the smallest chunk any launch shape uses (128 bins)
+  const size_t nchunk = (size_t)((K + 127) / 128);
   bool ok = true;
   ok = ok && dalloc(&c->f, K) == hipSuccess && dalloc(&c->nk, K) == hipSuccess;
   ok = ok && dalloc(&c->D, 3 * (size_t)K) == hipSuccess && dalloc(&c->R, 3 * (size_t)K) == hipSuccess;
@@ -280,6 +281,69 @@ lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st, double* lo
   if (st->n_states == 0) return LPS_OK;
   if (!logL) return LPS_E_NULL;
   return lps::launch_plain(ctx, st, logL, status, (hipStream_t)stream) == hipSuccess ? LPS_OK : LPS_E_DEVICE;
+}
+
+lps_status lps_set_launch(lps_ctx* ctx, lps_precision prec, int32_t bins_per_lane, int32_t states_per_tile) {
+  if (!ctx) return LPS_E_NULL;
+  if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
+  if (bins_per_lane != 0 && !lps::valid_bins_per_lane(prec, bins_per_lane)) return LPS_E_SHAPE;
+  if (states_per_tile < 0 || states_per_tile > 4096) return LPS_E_SHAPE;
+  ctx->fwd_shape[prec == LPS_MIXED ? 1 : 0] = {bins_per_lane, states_per_tile};
+  return LPS_OK;
+}
+
+lps_status lps_get_launch(lps_ctx* ctx, lps_precision prec, int32_t n_states, int32_t* bins_per_lane,
+                          int32_t* states_per_tile) {
+  if (!ctx || !bins_per_lane || !states_per_tile) return LPS_E_NULL;
+  if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
+  if (n_states < 1) return LPS_E_SHAPE;
+  const lps::LaunchShape sh = lps::forward_shape(ctx, prec, n_states);
+  *bins_per_lane = sh.bins_per_lane;
+  *states_per_tile = sh.tile;
+  return LPS_OK;
+}
+
+lps_status lps_autotune(lps_ctx* ctx, const lps_states* st, lps_precision prec, int32_t reps, double* best_ms,
+                        void* stream) {
+  lps_status r = check_states(ctx, st);
+  if (r != LPS_OK) return r;
+  if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
+  if (st->n_states == 0 || reps < 1) return LPS_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  const int n = st->n_states;
+  double* logL = nullptr;
+  if (hipMalloc((void**)&logL, (size_t)n * sizeof(double)) != hipSuccess) return LPS_E_NOMEM;
+  const int bpl[2][2] = {{2, 4}, {4, 8}};
+  const int tiles[] = {0, 16, 32, 64, 128, 256};
+  const int pi = prec == LPS_MIXED ? 1 : 0;
+  const lps::LaunchShape saved = ctx->fwd_shape[pi];
+  const int saved_timing = ctx->timing;
+  ctx->timing = 0;
+  hipEvent_t e0 = ctx->ev0, e1 = ctx->ev1;
+  double best = 1e300;
+  lps::LaunchShape best_sh = saved;
+  bool ok = true;
+  for (int bi = 0; bi < 2 && ok; ++bi) {
+    for (int ti = 0; ti < 6 && ok; ++ti) {
+      if (tiles[ti] > n) continue;
+      ctx->fwd_shape[pi] = {bpl[pi][bi], tiles[ti]};
+      ok = lps::launch_forward(ctx, st, prec, logL, nullptr, s) == hipSuccess;   // warm-up
+      ok = ok && hipEventRecord(e0, s) == hipSuccess;
+      for (int k = 0; k < reps && ok; ++k) ok = lps::launch_forward(ctx, st, prec, logL, nullptr, s) == hipSuccess;
+      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      float ms = 0.f;
+      ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (ok && ms / reps < best) {
+        best = ms / reps;
+        best_sh = ctx->fwd_shape[pi];
+      }
+    }
+  }
+  (void)hipFree(logL);
+  ctx->timing = saved_timing;
+  ctx->fwd_shape[pi] = ok ? best_sh : saved;
+  if (best_ms) *best_ms = ok ? best : -1.0;
+  return ok ? LPS_OK : LPS_E_DEVICE;
 }
 
 lps_status lps_set_timing(lps_ctx* ctx, int enable) {

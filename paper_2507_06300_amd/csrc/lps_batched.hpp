@@ -43,6 +43,13 @@ __device__ inline double readlane_r<double>(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Orders LDS writes and reads of one wavefront (lanes exchange data through LDS).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Number of interior breakpoints bx[1 .. ni-1] that are <= v (binary search).
 __device__ inline int count_le(const double* __restrict__ bxs, int ni, double v) {
   int lo = 0, hi = ni - 1;

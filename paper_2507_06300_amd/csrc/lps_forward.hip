@@ -25,7 +25,7 @@ namespace {
 
 template <typename R, int MODE, int NCH, bool FG, int B>
 __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int n_tiles, int tile, int K,
-                                                 int k_pad, const R* __restrict__ tab,
+                                                 int k_pad, int ref_chunk, const R* __restrict__ tab,
                                                  const double* __restrict__ x64, const double* __restrict__ bx,
                                                  const R* __restrict__ coef, const int32_t* __restrict__ n_int,
                                                  const StateScalars* __restrict__ scal,
@@ -35,9 +35,12 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   constexpr int CH = kWave * B;
   constexpr int SUB = kWave / G;            // states whose pieces one wave locates at once
   constexpr bool kMixed = sizeof(R) == 4;
+  // per-state lane partials, transposed: red[source lane][state of the sub-tile]
+  __shared__ double red[kWavesPerBlock][kWave * SUB];
   const int lane = threadIdx.x & (kWave - 1);
   // wave-uniform work-item index: keeps all per-state addressing scalar
-  const int item = blockIdx.x * kWavesPerBlock + uniform(threadIdx.x >> 6);
+  const int wv = uniform(threadIdx.x >> 6);
+  const int item = blockIdx.x * kWavesPerBlock + wv;
   const int chunk = item % n_chunks;
   const int t = item / n_chunks;
   if (t >= n_tiles) return;
@@ -64,6 +67,8 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   const int klast = min(kbase + CH, K) - 1;
   const double xf = x64[kbase];
   const double xl = x64[klast];
+  // abscissa origin of the single-precision table rows (start of their block)
+  const double xo = kMixed ? x64[(kbase / ref_chunk) * ref_chunk] : 0.0;
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       pc = cf[2];
       pd = cf[3];
       const double b0 = bx[pbase + pi0];
-      poff = kMixed ? (R)(xf - b0) : (R)(-b0);
+      poff = kMixed ? (R)(xo - b0) : (R)(-b0);
     }
     // per-state scalars on the lanes of group 0
     R pw0 = 0, pw1 = 0, pw2 = 0;
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     for (int q = 0; q < nsub; ++q) {
       const int s = sub + q;
       if (__builtin_amdgcn_readlane(pni, q * G) == 0) {   // invalid state: the finaliser reports it
-        if (lane == 0) partial[(size_t)s * n_chunks + chunk] = 0.0;
+        red[wv][lane * SUB + q] = 0.0;
         continue;
       }
       const R w_oms = readlane_r(pw0, q * G), w_tm = readlane_r(pw1, q * G), e_fg = readlane_r(pw2, q * G);
@@ -127,8 +132,8 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
             const R* cf = coef + (base + j) * 4;
             const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
             const double bj = bx[base + j];
-            const R off = kMixed ? (R)(xf - bj) : (R)(-bj);
-            const R lim = kMixed ? (R)(bj - xf) : (R)bj;   // bin is in piece j when xr >= lim
+            const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
+            const R lim = kMixed ? (R)(bj - xo) : (R)bj;   // bin is in piece j when xr >= lim
 #pragma unroll
             for (int b = 0; b < B; ++b) {
               const R tt = xr[b] + off;
@@ -160,7 +165,7 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
           }
         }
       }
-      double acc = 0.0;
+      R vb[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         // One reciprocal and one logarithm per bin for all channels:
@@ -177,9 +182,14 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
           const R num = S[2][b] * (ND[1][b] * S[0][b] + ND[0][b] * S[1][b]) + ND[2][b] * P01;
           v = num * Math<R>::rcp_(P) + NL[b] * Math<R>::log2_(P);
         }
-        acc += (double)v;
+        vb[b] = v;
       }
-      acc = wave_sum(acc);
+      // pairwise sum of the lane's bins, then one double-precision partial per lane
+#pragma unroll
+      for (int w = 1; w < B; w <<= 1)
+#pragma unroll
+        for (int b = 0; b + w < B; b += 2 * w) vb[b] += vb[b + w];
+      double acc = (double)vb[0];
       if (!isfinite(acc)) {
         // A channel product left the floating-point range (an extreme state):
         // redo the chunk with one reciprocal and logarithm per channel, so that
@@ -195,10 +205,18 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
           }
           acc += (double)v;
         }
-        acc = wave_sum(acc);
       }
-      if (lane == 0) partial[(size_t)s * n_chunks + chunk] = acc;
+      red[wv][lane * SUB + q] = acc;
     }
+    // lane q adds the 64 lane partials of state sub + q in a fixed order
+    wave_lds_sync();
+    if (lane < nsub) {
+      double sum = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < kWave; ++i) sum += red[wv][i * SUB + lane];
+      partial[(size_t)(sub + lane) * n_chunks + chunk] = sum;
+    }
+    wave_lds_sync();
   }
 }
 
@@ -229,9 +247,10 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
   const int items = n_chunks * n_tiles;
   dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
   const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
-#define LPS_FWD(MODE, NCH, FG)                                                                            \
-  hipLaunchKernelGGL((k_forward<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,   \
-                     ctx->n_bins, k_pad, tab, ctx->x, ctx->bx, coef, ctx->n_int, ctx->scal, ctx->partial)
+#define LPS_FWD(MODE, NCH, FG)                                                                              \
+  hipLaunchKernelGGL((k_forward<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,     \
+                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->n_int, ctx->scal,      \
+                     ctx->partial)
   const bool fg = L.has_fg != 0;
   if (L.mode == kSplit && L.nch == 2 && !fg) LPS_FWD(kSplit, 2, false);
   else if (L.mode == kSplit && L.nch == 2 && fg) LPS_FWD(kSplit, 2, true);
@@ -249,14 +268,25 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
 
 }  // namespace
 
-// States per tile: enough work items to fill the chip, at most 64 states.
-static int pick_tile(int n_states, int n_chunks) {
+// States per tile: enough work items to fill the chip, at most 256 states.
+int auto_tile(int n_states, int n_chunks) {
   const long target_items = 8192;   // ~32 waves per CU
   long tile = ((long)n_states * n_chunks) / target_items;
   if (tile < 1) tile = 1;
-  if (tile > 64) tile = 64;
+  if (tile > 256) tile = 256;
   if (tile > n_states) tile = n_states;
   return (int)tile;
+}
+
+// Launch shape of the batched forward kernel for one precision.
+LaunchShape forward_shape(const lps_ctx* ctx, lps_precision prec, int n_states) {
+  LaunchShape sh = ctx->fwd_shape[prec == LPS_MIXED ? 1 : 0];
+  if (sh.bins_per_lane == 0) sh.bins_per_lane = prec == LPS_MIXED ? kB32 : kB64;
+  const int chunk = kWave * sh.bins_per_lane;
+  const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
+  if (sh.tile == 0) sh.tile = auto_tile(n_states, n_chunks);
+  if (sh.tile > n_states) sh.tile = n_states;
+  return sh;
 }
 
 hipError_t launch_forward(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL, uint32_t* status,
@@ -265,19 +295,31 @@ hipError_t launch_forward(lps_ctx* ctx, const lps_states* st, lps_precision prec
   hipError_t e = launch_coeffs(ctx, st, s);
   if (e != hipSuccess) return e;
   const bool mixed = prec == LPS_MIXED;
-  const int n_chunks = mixed ? ctx->n_chunks32 : ctx->n_chunks64;
-  const int tile = pick_tile(n, n_chunks);
-  const int n_tiles = (n + tile - 1) / tile;
+  const LaunchShape sh = forward_shape(ctx, prec, n);
+  const int chunk = kWave * sh.bins_per_lane;
+  const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
+  const int n_tiles = (n + sh.tile - 1) / sh.tile;
   timing_begin(ctx, s);
-  if (mixed)
-    e = dispatch<float, kB32>(ctx, n, n_chunks, n_tiles, tile, ctx->tab32, ctx->coef32, s);
-  else
-    e = dispatch<double, kB64>(ctx, n, n_chunks, n_tiles, tile, ctx->tab64, ctx->coef64, s);
+  if (mixed) {
+    if (sh.bins_per_lane == 4)
+      e = dispatch<float, 4>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s);
+    else
+      e = dispatch<float, 8>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s);
+  } else {
+    if (sh.bins_per_lane == 2)
+      e = dispatch<double, 2>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s);
+    else
+      e = dispatch<double, 4>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s);
+  }
   if (e != hipSuccess) return e;
   timing_end(ctx, s);
   hipLaunchKernelGGL(k_finalize, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kWave * kWavesPerBlock), 0,
                      s, n, n_chunks, ctx->partial, ctx->c0, ctx->status_ws, logL, status);
   return hipGetLastError();
+}
+
+bool valid_bins_per_lane(lps_precision prec, int b) {
+  return prec == LPS_MIXED ? (b == 4 || b == 8) : (b == 2 || b == 4);
 }
 
 }  // namespace lps

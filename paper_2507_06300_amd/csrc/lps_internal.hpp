@@ -67,6 +67,13 @@ __host__ __device__ inline int tab_k(int term, int c, int nch) { return 1 + term
 __host__ __device__ inline int tab_nd(int c, int n_terms, int nch) { return 1 + n_terms * nch + c; }
 __host__ __device__ inline int tab_nl(int n_terms, int nch) { return 1 + n_terms * nch + nch; }
 
+// Launch shape of a batched kernel: bins per lane (chunk = 64 x that) and
+// states per tile; 0 selects the built-in default.
+struct LaunchShape {
+  int bins_per_lane;
+  int tile;
+};
+
 // Per-state scalars written by the coefficient kernel.
 struct StateScalars {
   double w_oms;     // (A_oms / ref)^2   (shared / paper modes)
@@ -124,6 +131,9 @@ struct lps_ctx {
   int32_t plain_blocks;
   uint32_t* sticky;    // [1] device error flags
 
+  // launch shapes of the forward kernel: [0] FP64, [1] mixed
+  lps::LaunchShape fwd_shape[2];
+
   // timing
   int timing;
   hipEvent_t ev0, ev1;
@@ -145,6 +155,8 @@ hipError_t launch_plain(lps_ctx* ctx, const lps_states* st, double* logL, uint32
 hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL,
                        double* dparams, double* dkx, double* dky, uint32_t* status, hipStream_t s);
 size_t grad_workspace_bytes(const lps_ctx* ctx);
+LaunchShape forward_shape(const lps_ctx* ctx, lps_precision prec, int n_states);
+bool valid_bins_per_lane(lps_precision prec, int b);
 
 // Chunk geometry of the batched kernels.
 constexpr int kWavesPerBlock = 4;

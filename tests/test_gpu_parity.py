@@ -257,3 +257,28 @@ def test_mixed_extreme_states_keep_fp64_status(lps):
     assert np.all(np.abs(a[ok] - b[ok]) <= 1e-6 * np.abs(a[ok]))
     ref = C.oracle_loglikes(ds, D, ext)
     assert np.all(np.abs(a[ok] - ref[ok]) <= 1e-9 * np.abs(ref[ok]))
+
+
+@pytest.mark.parametrize("prec,shapes", [("fp64", [(2, 0), (4, 0), (2, 7), (4, 64)]),
+                                         ("mixed", [(4, 0), (8, 0), (4, 5), (8, 128)])])
+def test_every_launch_shape_matches_oracle(lps, prec, shapes):
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=2999, layout="split")
+    sb = W.make_states(name, ds, n_states=70, inbetween=(0, 25))
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    ref = C.oracle_loglikes(ds, D, sb)
+    tol = 1e-9 * np.abs(ref) if prec == "fp64" else C.mixed_tolerance(ds, D, sb, range(sb.n))
+    first = None
+    for b, t in shapes:
+        ctx.set_launch(prec, b, t)
+        assert ctx.get_launch(prec, sb.n)[0] == b
+        got = ctx.loglike_batch(st, prec)[0].cpu().numpy()
+        assert np.all(np.abs(got - ref) <= tol), (b, t)
+        first = got if first is None else first
+    with pytest.raises(lps.LpsError):
+        ctx.set_launch(prec, 3, 0)
+    ms, shape = ctx.autotune(st, prec, reps=2)
+    assert ms > 0 and shape[0] in (2, 4, 8)
+    got = ctx.loglike_batch(st, prec)[0].cpu().numpy()
+    assert np.all(np.abs(got - ref) <= tol)
