@@ -92,7 +92,7 @@ def parse():
     p.add_argument("--workload", default="year_912085bins_4096states")
     p.add_argument("--plain-states", type=int, default=64,
                    help="states timed on the plain FP64 per-state path (per-state cost is uniform)")
-    p.add_argument("--cpu-states", type=int, default=48, help="states in the CPU oracle sample")
+    p.add_argument("--cpu-states", type=int, default=64, help="states in the CPU oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-grad", action="store_true")
