@@ -116,6 +116,10 @@ typedef struct {
                                 4..k_max is Akima; 1 is invalid. */
   const double* knot_x;      /* log10 f of each knot, edges included, strictly increasing */
   const double* knot_y;      /* knot heights (P is in dex: the factor is 10^P) */
+  const int32_t* knot_cnt;   /* NULL: packed CSR as above.  Otherwise padded CSR: spline i
+                                (= s*n_spl+j) owns knot_cnt[i] knots starting at knot_off[i],
+                                so slots may have spare capacity (used by the sampler to
+                                edit knots in place); knot_off then needs n_states*n_spl entries. */
 } lps_states;
 
 /*
@@ -203,6 +207,60 @@ lps_status lps_autotune(lps_ctx* ctx, const lps_states* st /*[host]*/, lps_preci
  */
 lps_status lps_set_timing(lps_ctx* ctx, int enable);
 lps_status lps_kernel_time_ms(lps_ctx* ctx, double* total_ms /*[host]*/, int32_t* launches /*[host]*/);
+
+/* ------------------------------------------------------------------------
+ * Parallel-tempered reversible-jump sampler sweep on the device.
+ *
+ * Chains c = t * n_walkers + w.  Each sweep: a preconditioned Langevin
+ * (MALA) move of all continuous parameters driven by the adjoint gradient,
+ * a birth/death move of one in-between knot of one spline per chain (births
+ * from the priors of Table I; Sec. "Power spectral density breakdown"),
+ * FP64 tempered Metropolis-Hastings decisions, and swaps between adjacent
+ * temperatures.  A sweep is a fixed launch sequence on one stream that never
+ * allocates or synchronises, so sweeps may be captured into a HIP graph.
+ * Random numbers: Philox4x32-10 keyed by the seed, indexed by (chain, sweep,
+ * purpose); the sweep counter lives in device memory.
+ * ------------------------------------------------------------------------ */
+typedef struct lps_sampler lps_sampler;
+
+typedef struct {
+  int32_t n_walkers;
+  int32_t n_temps;
+  const double* betas;        /* [host] n_temps inverse temperatures in [0, 1] */
+  const double* temp_scales;  /* [host] per-temperature step multipliers, or NULL for min(1/sqrt(beta), 1e3) */
+  uint64_t seed;
+  int32_t k_in_max;           /* maximum in-between knots per spline; k_in_max + 2 <= k_max */
+  double step;                /* Langevin step multiplier (> 0) */
+  lps_precision precision;    /* precision of the likelihood and gradient evaluations */
+} lps_sampler_desc;
+
+/* Allocate chain storage for n_walkers * n_temps chains (<= max_grad_states of ctx). */
+lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* desc /*[host]*/, lps_sampler** out /*[host]*/);
+lps_status lps_sampler_destroy(lps_sampler* sm);
+
+/* Load the chains from a packed-CSR batch (n_states = chains, every spline with
+ * 2..k_in_max+2 knots), set the sweep counter, evaluate logL and gradients.
+ * Synchronises.  Returns LPS_E_CAPACITY if a spline does not fit its slot. */
+lps_status lps_sampler_set_state(lps_sampler* sm, const lps_states* init /*[host]*/, uint64_t sweep_index,
+                                 void* stream);
+
+/* Run n_sweeps sweeps (asynchronous, graph-capturable). */
+lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream);
+
+/* Copy the current chains out (device outputs, any may be NULL): params [P][C],
+ * padded-CSR knot_off/knot_cnt [C*n_spl] and knot_x/knot_y [C*n_spl*(k_in_max+2)],
+ * logL [C]; sweep_index [host] (synchronises when requested). */
+lps_status lps_sampler_get_state(lps_sampler* sm, double* params, int32_t* knot_off, int32_t* knot_cnt,
+                                 double* knot_x, double* knot_y, double* logL, uint64_t* sweep_index /*[host]*/,
+                                 void* stream);
+
+/* Move statistics [host] uint32[4][n_temps][2] = (proposed, accepted) for the
+ * kinds Langevin, birth, death, swap (swap counted at the lower temperature).  Synchronises. */
+lps_status lps_sampler_counters(lps_sampler* sm, uint32_t* counters /*[host]*/, void* stream);
+
+/* The sampler's generator: out[4i..4i+3] = Philox4x32-10(counter = (first + i) as
+ * (low word, high word, 0, 0), key = (seed low, seed high)).  Device output. */
+lps_status lps_philox4x32_10(uint64_t seed, uint64_t first_counter, int32_t n, uint32_t* out, void* stream);
 
 /* Synchronise the stream and report the sticky device error flags (0 = none). */
 lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags /*[host]*/);

@@ -44,14 +44,22 @@ class _Desc(ctypes.Structure):
                 ("max_grad_states", ctypes.c_int32)]
 
 
+class _SamplerDesc(ctypes.Structure):
+    _fields_ = [("n_walkers", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("betas", ctypes.c_void_p),
+                ("temp_scales", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("k_in_max", ctypes.c_int32),
+                ("step", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
 class _States(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_int32), ("params", ctypes.c_void_p), ("knot_off", ctypes.c_void_p),
-                ("knot_x", ctypes.c_void_p), ("knot_y", ctypes.c_void_p)]
+                ("knot_x", ctypes.c_void_p), ("knot_y", ctypes.c_void_p), ("knot_cnt", ctypes.c_void_p)]
 
 
 SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
            "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error", "lps_strerror",
-           "lps_chunk_bins", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune"]
+           "lps_chunk_bins", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune",
+           "lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
+           "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10"]
 
 _lib = None
 
@@ -88,6 +96,16 @@ def lib():
     L.lps_get_launch.restype = st
     L.lps_autotune.argtypes = [vp, ctypes.POINTER(_States), ctypes.c_int, i32, dp, vp]
     L.lps_autotune.restype = st
+    L.lps_sampler_create.argtypes = [vp, ctypes.POINTER(_SamplerDesc), ctypes.POINTER(vp)]
+    L.lps_sampler_destroy.argtypes = [vp]
+    L.lps_sampler_set_state.argtypes = [vp, ctypes.POINTER(_States), ctypes.c_uint64, vp]
+    L.lps_sampler_sweep.argtypes = [vp, i32, vp]
+    L.lps_sampler_get_state.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]
+    L.lps_sampler_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
+    L.lps_philox4x32_10.argtypes = [ctypes.c_uint64, ctypes.c_uint64, i32, vp, vp]
+    for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
+                 "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10"]:
+        getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
         getattr(L, name).restype = st
@@ -119,11 +137,15 @@ def _stream(stream):
 
 @dataclass
 class States:
-    """A state batch resident on the device (params [P][n], CSR knots)."""
+    """A state batch resident on the device (params [P][n], CSR knots).
+
+    knot_cnt = None: packed CSR (counts are offset differences); otherwise a
+    padded layout where spline i owns knot_cnt[i] knots from knot_off[i]."""
     params: torch.Tensor
     knot_off: torch.Tensor
     knot_x: torch.Tensor
     knot_y: torch.Tensor
+    knot_cnt: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
@@ -131,7 +153,7 @@ class States:
 
     def _c(self):
         return _States(self.n, self.params.data_ptr(), self.knot_off.data_ptr(), self.knot_x.data_ptr(),
-                       self.knot_y.data_ptr())
+                       self.knot_y.data_ptr(), None if self.knot_cnt is None else self.knot_cnt.data_ptr())
 
 
 class Context:
@@ -271,6 +293,91 @@ def valu_probe(device=0):
 
 def chunk_bins(precision="fp64") -> int:
     return int(lib().lps_chunk_bins(_PREC.get(precision, precision)))
+
+
+def philox4x32_10(seed: int, first_counter: int, n: int, device="cuda"):
+    """The sampler's generator on the device: uint32 [n][4] (as int64 tensor)."""
+    out = torch.empty(4 * n, dtype=torch.int32, device=device)
+    _check(lib().lps_philox4x32_10(ctypes.c_uint64(seed), ctypes.c_uint64(first_counter), int(n), _ptr(out),
+                                   _stream(None)), "lps_philox4x32_10")
+    return (out.to(torch.int64) & 0xFFFFFFFF).view(n, 4)
+
+
+class Sampler:
+    """Parallel-tempered reversible-jump sweeps on the device (wraps lps_sampler_*)."""
+
+    KINDS = ("langevin", "birth", "death", "swap")
+
+    def __init__(self, ctx: Context, n_walkers, betas, seed=1, k_in_max=10, step=0.05, precision="mixed",
+                 temp_scales=None):
+        self.ctx = ctx
+        self.W = int(n_walkers)
+        self.betas = np.ascontiguousarray(betas, dtype=np.float64)
+        self.T = int(self.betas.size)
+        self.C = self.W * self.T
+        self.KC = int(k_in_max) + 2
+        self._scales = None if temp_scales is None else np.ascontiguousarray(temp_scales, dtype=np.float64)
+        d = _SamplerDesc()
+        d.n_walkers, d.n_temps = self.W, self.T
+        d.betas = self.betas.ctypes.data
+        d.temp_scales = None if self._scales is None else self._scales.ctypes.data
+        d.seed = int(seed)
+        d.k_in_max = int(k_in_max)
+        d.step = float(step)
+        d.precision = _PREC.get(precision, precision)
+        h = ctypes.c_void_p()
+        _check(lib().lps_sampler_create(ctx._h, ctypes.byref(d), ctypes.byref(h)), "lps_sampler_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lps_sampler_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, st: States, sweep_index=0, stream=None):
+        c = st._c()
+        _check(lib().lps_sampler_set_state(self._h, ctypes.byref(c), ctypes.c_uint64(int(sweep_index)),
+                                           _stream(stream)), "lps_sampler_set_state")
+
+    def sweep(self, n=1, stream=None):
+        _check(lib().lps_sampler_sweep(self._h, int(n), _stream(stream)), "lps_sampler_sweep")
+
+    def get_state(self, stream=None):
+        dev, C, NS, KC = self.ctx.device, self.C, self.ctx.n_spl, self.KC
+        params = torch.empty((self.ctx.n_params, C), dtype=torch.float64, device=dev)
+        off = torch.empty(C * NS, dtype=torch.int32, device=dev)
+        cnt = torch.empty(C * NS, dtype=torch.int32, device=dev)
+        kx = torch.empty(C * NS * KC, dtype=torch.float64, device=dev)
+        ky = torch.empty_like(kx)
+        logL = torch.empty(C, dtype=torch.float64, device=dev)
+        sw = ctypes.c_uint64()
+        _check(lib().lps_sampler_get_state(self._h, _ptr(params), _ptr(off), _ptr(cnt), _ptr(kx), _ptr(ky),
+                                           _ptr(logL), ctypes.byref(sw), _stream(stream)), "lps_sampler_get_state")
+        return {"params": params, "knot_off": off, "knot_cnt": cnt, "knot_x": kx, "knot_y": ky, "logL": logL,
+                "sweep": sw.value}
+
+    def packed_state(self, stream=None):
+        """Current chains as a packed-CSR States batch (for checkpoints and set_state)."""
+        s = self.get_state(stream)
+        off, cnt = s["knot_off"].cpu().numpy(), s["knot_cnt"].cpu().numpy()
+        kx, ky = s["knot_x"].cpu().numpy(), s["knot_y"].cpu().numpy()
+        xs = [kx[o:o + c] for o, c in zip(off, cnt)]
+        ys = [ky[o:o + c] for o, c in zip(off, cnt)]
+        poff = np.zeros(len(cnt) + 1, dtype=np.int32)
+        poff[1:] = np.cumsum(cnt)
+        st = self.ctx.states(s["params"], poff, np.concatenate(xs), np.concatenate(ys))
+        return st, s["sweep"], s["logL"]
+
+    def counters(self, stream=None):
+        buf = (ctypes.c_uint32 * (4 * self.T * 2))()
+        _check(lib().lps_sampler_counters(self._h, buf, _stream(stream)), "lps_sampler_counters")
+        return np.frombuffer(buf, dtype=np.uint32).reshape(4, self.T, 2).copy()
 
 
 class LogLikeFn(torch.autograd.Function):

@@ -19,14 +19,15 @@ namespace {
 
 __global__ void k_coeffs(int n_states, int n_spl, int k_max, Layout lay, int n_params,
                          const double* __restrict__ params, const int32_t* __restrict__ off,
-                         const double* __restrict__ kx, const double* __restrict__ ky, double x_first,
+                         const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
+                         const double* __restrict__ ky, double x_first,
                          double x_last, double x_knee, double* __restrict__ bx, double* __restrict__ coef64,
                          float* __restrict__ coef32, int32_t* __restrict__ n_int, StateScalars* __restrict__ scal,
                          uint32_t* __restrict__ status_ws) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_states) return;
   const int G = lay.n_grp;
-  uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kx, ky, x_first, x_last);
+  uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kcnt, kx, ky, x_first, x_last);
   status_ws[s] = st;
   if (st) {
     for (int g = 0; g < G; ++g) n_int[s * G + g] = 0;
@@ -55,8 +56,7 @@ __global__ void k_coeffs(int n_states, int n_spl, int k_max, Layout lay, int n_p
     const size_t base = (size_t)(s * G + g) * kMaxKnots;
     int cnt = 0, a0 = 0;
     if (j >= 0) {
-      a0 = off[s * n_spl + j];
-      cnt = off[s * n_spl + j + 1] - a0;
+      knot_range(off, kcnt, s * n_spl + j, a0, cnt);
     }
     if (cnt == 0) {
       bx[base] = x_first;
@@ -101,7 +101,8 @@ hipError_t launch_coeffs(lps_ctx* ctx, const lps_states* st, hipStream_t s) {
   const int n = st->n_states;
   const int tpb = 64;
   hipLaunchKernelGGL(k_coeffs, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, s, n, ctx->n_spl, ctx->k_max, ctx->lay,
-                     ctx->n_params, st->params, st->knot_off, st->knot_x, st->knot_y, ctx->x_first, ctx->x_last,
+                     ctx->n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->x_first,
+                     ctx->x_last,
                      log10(ctx->f_knee), ctx->bx, ctx->coef64, ctx->coef32, ctx->n_int, ctx->scal, ctx->status_ws);
   return hipGetLastError();
 }

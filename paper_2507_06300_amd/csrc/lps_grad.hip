@@ -25,6 +25,7 @@
 
 #include "lps_batched.hpp"
 #include "lps_spline.hpp"
+#include "lps_validate.hpp"
 
 namespace lps {
 namespace {
@@ -490,7 +491,7 @@ __device__ void spline_backward(const double* __restrict__ x, const double* __re
 
 __global__ void k_grad_finish(int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay,
                               double x_knee, const double* __restrict__ params, const int32_t* __restrict__ off,
-                              const double* __restrict__ kx, const double* __restrict__ ky,
+                              const int32_t* __restrict__ kcnt, const double* __restrict__ kx, const double* __restrict__ ky,
                               const int32_t* __restrict__ n_int, const double* __restrict__ bx,
                               const double* __restrict__ rec, const double* __restrict__ moments,
                               const double* __restrict__ c0, const uint32_t* __restrict__ status_ws,
@@ -514,8 +515,9 @@ __global__ void k_grad_finish(int n_states, int n_spl, int n_params, int NV, int
     logL[s] = -INFINITY;
     for (int p = 0; p < n_params; ++p) dparams[p * (size_t)n_states + s] = 0.0;
     for (int j = 0; j < n_spl; ++j) {
-      const int a = off[s * n_spl + j], b = off[s * n_spl + j + 1];
-      for (int i = a; a >= 0 && i < b; ++i) {
+      int a, cn;
+      knot_range(off, kcnt, s * n_spl + j, a, cn);
+      for (int i = a; a >= 0 && i < a + cn; ++i) {
         dkx[i] = 0.0;
         dky[i] = 0.0;
       }
@@ -554,8 +556,8 @@ __global__ void k_grad_finish(int n_states, int n_spl, int n_params, int NV, int
   // spline knots: sum the moments of every group fed by the spline
   double mom[kMaxKnots * 4];
   for (int j = 0; j < n_spl; ++j) {
-    const int a = off[s * n_spl + j];
-    const int n = off[s * n_spl + j + 1] - a;
+    int a, n;
+    knot_range(off, kcnt, s * n_spl + j, a, n);
     if (n == 0) continue;
     for (int i = 0; i < (n - 1) * 4; ++i) mom[i] = 0.0;
     for (int g = 0; g < G; ++g) {
@@ -640,7 +642,8 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
   hipLaunchKernelGGL(k_grad_reduce, dim3((n * G + 127) / 128), dim3(128), 0, s, n, G, NV, n_chunks, ctx->n_int, rec,
                      gidx, glast, ctx->moments);
   hipLaunchKernelGGL(k_grad_finish, dim3((n + 63) / 64), dim3(64), 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
-                     ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_x, st->knot_y, ctx->n_int,
+                     ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
+                     ctx->n_int,
                      ctx->bx, rec, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams, dkx, dky, status);
   return hipGetLastError();
 }

@@ -43,8 +43,8 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
     int K, const double* __restrict__ f, const double* __restrict__ nk, const double* __restrict__ D,
     const double* __restrict__ R, const double* __restrict__ Rfg, double L, double f_knee, int n_spl, int k_max,
     Route route, int n_states, int n_params, int s, const double* __restrict__ params,
-    const int32_t* __restrict__ off, const double* __restrict__ kx, const double* __restrict__ ky,
-    double* __restrict__ part) {
+    const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
+    const double* __restrict__ ky, double* __restrict__ part) {
   __shared__ double red[kPlainBlock];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   double l = 0.0;
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
     const double hfac = h2omega * 3.0 * kH0PerH * kH0PerH / (4.0 * kPi * kPi * fk * fk * fk);
     double P[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j < n_spl; ++j) {
-      const int a = off[s * n_spl + j];
-      const int n = off[s * n_spl + j + 1] - a;
+      int a, n;
+      knot_range(off, kcnt, s * n_spl + j, a, n);
       P[j] = (a >= 0) ? spline_value(kx + a, ky + a, n, k_max, xk) : 0.0;
     }
     const double ufg = n_params > 4 ? params[LPS_P_UFG * (size_t)n_states + s] : 0.0;
@@ -96,8 +96,9 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
 
 __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
     int n_blocks, const double* __restrict__ part, int s, int n_states, int n_spl, int k_max, int n_params,
-    const double* __restrict__ params, const int32_t* __restrict__ off, const double* __restrict__ kx,
-    const double* __restrict__ ky, double x_first, double x_last, double* __restrict__ logL,
+    const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+    const double* __restrict__ kx, const double* __restrict__ ky, double x_first, double x_last,
+    double* __restrict__ logL,
     uint32_t* __restrict__ status) {
   __shared__ double red[kPlainBlock];
   double acc = 0.0;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kx, ky, x_first, x_last);
+    uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kcnt, kx, ky, x_first, x_last);
     const double v = -red[0];
     if (st == 0 && !isfinite(v)) st |= LPS_ST_PSD;
     logL[s] = st ? -INFINITY : v;
@@ -130,9 +131,10 @@ hipError_t launch_plain(lps_ctx* ctx, const lps_states* st, double* logL, uint32
   for (int i = 0; i < n; ++i) {
     hipLaunchKernelGGL(k_plain_bins, dim3(nb), dim3(kPlainBlock), 0, s, K, ctx->f, ctx->nk, ctx->D, ctx->R,
                        ctx->Rfg, ctx->arm_length, ctx->f_knee, ctx->n_spl, ctx->k_max, route, n, ctx->n_params, i,
-                       st->params, st->knot_off, st->knot_x, st->knot_y, ctx->plain_part);
+                       st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->plain_part);
     hipLaunchKernelGGL(k_plain_finish, dim3(1), dim3(kPlainBlock), 0, s, nb, ctx->plain_part, i, n, ctx->n_spl,
-                       ctx->k_max, ctx->n_params, st->params, st->knot_off, st->knot_x, st->knot_y, ctx->x_first,
+                       ctx->k_max, ctx->n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
+                       ctx->x_first,
                        ctx->x_last, logL, status);
   }
   timing_end(ctx, s);

@@ -17,9 +17,17 @@ namespace lps {
 
 constexpr double kCoverSlack = 1e-9;
 
+// Knot range of spline slot i (= state * n_spl + spline): packed CSR when cnt is
+// NULL (count = off[i+1] - off[i]), padded CSR otherwise (count = cnt[i]).
+__device__ inline void knot_range(const int32_t* __restrict__ off, const int32_t* __restrict__ cnt, int i, int& a,
+                                  int& n) {
+  a = off[i];
+  n = cnt ? cnt[i] : off[i + 1] - a;
+}
+
 __device__ inline uint32_t validate_state(int s, int n_states, int n_spl, int k_max, int n_params,
                                           const double* __restrict__ params, const int32_t* __restrict__ off,
-                                          const double* __restrict__ kx, const double* __restrict__ ky,
+                                          const int32_t* __restrict__ kcnt, const double* __restrict__ kx, const double* __restrict__ ky,
                                           double x_first, double x_last) {
   uint32_t st = 0;
   for (int p = 0; p < n_params; ++p)
@@ -28,8 +36,8 @@ __device__ inline uint32_t validate_state(int s, int n_states, int n_spl, int k_
   const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
   if (!(a_oms > 0.0 && a_tm > 0.0)) st |= LPS_ST_AMPLITUDE;
   for (int j = 0; j < n_spl; ++j) {
-    const int a = off[s * n_spl + j];
-    const int cnt = off[s * n_spl + j + 1] - a;
+    int a, cnt;
+    knot_range(off, kcnt, s * n_spl + j, a, cnt);
     if (cnt == 0) continue;
     if (a < 0 || cnt < 0 || cnt == 1 || cnt > k_max) {
       st |= LPS_ST_COUNT;
