@@ -100,6 +100,9 @@ def parse():
     p.add_argument("--copy-check", action="store_true",
                    help="also run one 1 GiB device-to-device copy (HBM counter calibration)")
     p.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
+    p.add_argument("--sweeps", type=int, default=100,
+                   help="sampler sweeps timed on the sweep workload (0 skips the sampler leg)")
+    p.add_argument("--sweep-workload", default="sweep_250000bins_2048chains")
     p.add_argument("--launch", default="",
                    help="fixed launch shapes instead of autotuning, e.g. mixed=8x128,fp64=4x64")
     return p.parse_args()
@@ -307,6 +310,10 @@ def main():
         except lps.LpsError as e:
             result["grad"] = {"error": str(e)}
 
+    # --- sampler sweeps -------------------------------------------------------------
+    if args.sweeps > 0:
+        result["sampler"] = sampler_bench(torch, lps, W, args, dev)
+
     # --- CPU oracle baseline ------------------------------------------------------
     if not args.no_cpu:
         log("cpu oracle sample ...")
@@ -336,6 +343,58 @@ def grad_bench(torch, lps, W, args, dev):
         res[prec] = {"grad_evals_per_s": n / per, "state_bin_grad_evals_per_s": n * K / per,
                      "ms_per_call": per * 1e3}
         log(f"grad {prec}: {per * 1e3:.3f} ms/call, {n / per:.3e} grad evals/s")
+    return res
+
+
+def sampler_bench(torch, lps, W, args, dev):
+    """Graph-captured PT-RJMCMC sweeps: 128 walkers x 16 temperatures on the
+    250,000-bin workload with the foreground term, up to 40 in-between knots."""
+    name = args.sweep_workload
+    wl = W.WORKLOADS[name]
+    ds = W.make_dataset(name)
+    sb = W.make_states(name, ds)
+    K, n = ds.f.size, sb.n
+    n_temps = 16
+    n_walk = n // n_temps
+    betas = np.geomspace(1.0, 1e-4, n_temps)
+    ctx0 = lps.Context(ds.f, ds.nk, np.ones((3, K)), ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=1,
+                       device=dev, max_grad_states=0)
+    S0, _ = ctx0.psd_build(ctx0.states(ds.truth.params, ds.truth.knot_off, ds.truth.knot_x, ds.truth.knot_y))
+    D = S0[0] * torch.as_tensor(ds.chi, device=dev)
+    ctx0.close()
+    ctx = lps.Context(ds.f, ds.nk, D, ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=n, device=dev)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    k_in_max = wl.inbetween[1]
+    sm = lps.Sampler(ctx, n_walk, betas, seed=2025, k_in_max=k_in_max, step=0.05, precision="mixed")
+    sm.set_state(st)
+    per_graph = 10
+    sm.sweep(1)                                   # load every kernel before capture
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        sm.sweep(per_graph)
+    torch.cuda.synchronize()
+    reps = max(1, args.sweeps // per_graph)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    sweeps = reps * per_graph
+    cnt = sm.counters()
+    acc = {k: float(cnt[i, :, 1].sum()) / max(1.0, float(cnt[i, :, 0].sum())) for i, k in enumerate(sm.KINDS)}
+    ev = 2 * sweeps * n * K       # two gradient evaluations of every chain per sweep
+    log(f"sampler: {sweeps} sweeps in {sec:.2f} s ({sweeps / sec:.1f} sweeps/s), acceptance {acc}")
+    res = {"workload": name, "n_bins": K, "chains": n, "walkers": n_walk, "temperatures": n_temps,
+           "sweeps": sweeps, "seconds": sec, "sweeps_per_s": sweeps / sec, "ms_per_sweep": sec / sweeps * 1e3,
+           "state_bin_grad_evals_per_s": ev / sec, "acceptance": acc, "graph": f"{per_graph} sweeps per graph"}
+    sm.close()
+    ctx.close()
     return res
 
 

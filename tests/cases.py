@@ -32,9 +32,10 @@ def oracle_status(ds, sb, idx=None, k_max=64):
     return np.array([O.state_status(ds, sb.params[:, s], knots_of(sb, s), k_max) for s in idx])
 
 
-def make_context(lps, ds, D, max_states, k_max=64):
+def make_context(lps, ds, D, max_states, k_max=64, max_grad_states=None):
     return lps.Context(ds.f, ds.nk, D, ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, k_max=k_max,
-                       max_states=max_states, f_knee=ds.f_knee, arm_length=ds.arm_length)
+                       max_states=max_states, f_knee=ds.f_knee, arm_length=ds.arm_length,
+                       max_grad_states=max_grad_states)
 
 
 def device_states(ctx, sb):
