@@ -30,17 +30,13 @@ UNIT = "state·bin evals/s"
 
 # Algorithmic VALU work of the mixed batched kernel per state.bin for the
 # split layout with A and E merged (3 exponent groups, 2 distinct channels):
-#   per group   : t = x + off (1), Horner (3 FMA), exp2 (1 transcendental)
-#   assembly    : 2 channels x (1 mul + 2 FMA)
-#   likelihood  : 2 channels x (rcp, log2 transcendentals + 2 FMA)
-#   accumulate  : cvt f32->f64 + f64 add
-#   per group   : t = x + off, 3-FMA Horner, exp2                  -> 4 + 1 trans
+#   per group   : cubic in the bin abscissa (3 FMA) and exp2         -> 3 + 1 trans
 #   assembly    : 2 channels x 3 groups, one FMA each                -> 6
 #   likelihood  : P = S0 S1, num (mul + fma), rcp(P), log2(P S0),
-#                 v = num r + NL lg (mul + fma)                        -> 6 + 2 trans
-#   accumulate  : cvt f32->f64 + f64 add                              -> 2 x 2 slots
-MIXED_FP32_OPS = 3 * 4 + 6 + 6                      # 24 FP32 VALU instructions
-MIXED_FP64_SLOTS = 2 * 2                             # cvt + add at half rate
+#                 acc += num r, acc += NL lg                          -> 6 + 2 trans
+#   accumulate  : one add into the lane's partial                     -> 1
+MIXED_FP32_OPS = 3 * 3 + 6 + 6 + 1                  # 22 FP32 VALU instructions
+MIXED_FP64_SLOTS = 0                                 # FP64 work is per state and chunk, not per bin
 MIXED_TRANS_OPS = 3 + 2                              # exp2 x3, rcp, log2
 
 # Published MI355X FP32 vector peak: 157.3 TFLOP/s = 256 CUs x 128 FP32 FMA

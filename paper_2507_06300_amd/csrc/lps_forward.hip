@@ -18,6 +18,8 @@
 //   logL = C0 - sum_chunks partial.
 #include <math.h>
 
+#include <type_traits>
+
 #include "lps_batched.hpp"
 
 namespace lps {
@@ -27,16 +29,28 @@ template <typename R, int MODE, int NCH, bool FG, int B>
 __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int n_tiles, int tile, int K,
                                                  int k_pad, int ref_chunk, const R* __restrict__ tab,
                                                  const double* __restrict__ x64, const double* __restrict__ bx,
-                                                 const R* __restrict__ coef, const int32_t* __restrict__ n_int,
+                                                 const R* __restrict__ coef, const double* __restrict__ coef64,
+                                                 const int32_t* __restrict__ n_int,
                                                  const StateScalars* __restrict__ scal,
                                                  double* __restrict__ partial) {
   constexpr int G = Groups<MODE>::G;
   constexpr int NT = FG ? 4 : 3;
   constexpr int CH = kWave * B;
-  constexpr int SUB = kWave / G;            // states whose pieces one wave locates at once
   constexpr bool kMixed = sizeof(R) == 4;
-  // per-state lane partials, transposed: red[source lane][state of the sub-tile]
-  __shared__ double red[kWavesPerBlock][kWave * SUB];
+  // states whose pieces one wave locates at once (fewer for FP64 to bound LDS)
+  constexpr int SUB = (kWave / G) < (kMixed ? 32 : 16) ? (kWave / G) : (kMixed ? 32 : 16);
+  // When a wave's chunk is a whole table block (its rows hold x - x_chunk), each
+  // piece's cubic is re-expanded around the chunk start once per sub-tile, and
+  // the per-bin Horner runs directly on the table abscissa.
+  constexpr bool kLocalPoly = kMixed && CH == kChunk32;
+  constexpr bool kScalars = FG || MODE != kSplit;
+  // Per wave: the located piece of every (state, group) pair of the sub-tile
+  // (a, b, c, d, offset), the per-state scalars, and the per-state lane
+  // partials stored transposed (red[source lane][state]).
+  using Acc = typename std::conditional<kMixed, float, double>::type;
+  __shared__ R lcoef[kWavesPerBlock][kWave][5];
+  __shared__ R lscal[kWavesPerBlock][SUB][4];
+  __shared__ Acc red[kWavesPerBlock][kWave * SUB];
   const int lane = threadIdx.x & (kWave - 1);
   // wave-uniform work-item index: keeps all per-state addressing scalar
   const int wv = uniform(threadIdx.x >> 6);
@@ -74,38 +88,61 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     const int nsub = min(SUB, s_end - sub);
     // ---- locate: lane p owns the piece of (state sub + p / G, group p % G) ----
     const int ps = lane / G, pg = lane - (lane / G) * G;
-    const bool pv = ps < nsub;
+    const bool pv = ps < nsub && ps < SUB;
     const size_t pbase = (size_t)((sub + ps) * G + pg) * kMaxKnots;
     const int pni = pv ? n_int[(sub + ps) * G + pg] : 0;
     int pi0 = 0, pi1 = 0;
-    R pa = 0, pb = 0, pc = 0, pd = 0, poff = 0;
     if (pni > 0) {
       pi0 = count_le(bx + pbase, pni, xf);
       pi1 = count_le(bx + pbase, pni, xl);
-      const R* cf = coef + (pbase + pi0) * 4;
-      pa = cf[0];
-      pb = cf[1];
-      pc = cf[2];
-      pd = cf[3];
       const double b0 = bx[pbase + pi0];
-      poff = kMixed ? (R)(xo - b0) : (R)(-b0);
+      R rec[5];
+      if constexpr (kLocalPoly) {
+        // Q(x) = a + b t + c t^2 + d t^3, t = x - b0 = t0 + dx  ->  polynomial in dx = x - xo
+        const double* cf = coef64 + (pbase + pi0) * 4;
+        const double t0 = xo - b0;
+        const double a = cf[0], b = cf[1], c = cf[2], d = cf[3];
+        rec[0] = (R)(a + t0 * (b + t0 * (c + t0 * d)));
+        rec[1] = (R)(b + t0 * (2.0 * c + 3.0 * d * t0));
+        rec[2] = (R)(c + 3.0 * d * t0);
+        rec[3] = (R)d;
+        rec[4] = 0;
+      } else {
+        const R* cf = coef + (pbase + pi0) * 4;
+        rec[0] = cf[0];
+        rec[1] = cf[1];
+        rec[2] = cf[2];
+        rec[3] = cf[3];
+        rec[4] = kMixed ? (R)(xo - b0) : (R)(-b0);
+      }
+#pragma unroll
+      for (int i = 0; i < 5; ++i) lcoef[wv][lane][i] = rec[i];
     }
-    // per-state scalars on the lanes of group 0
-    R pw0 = 0, pw1 = 0, pw2 = 0;
-    if (pv && pg == 0) {
-      const StateScalars sc = scal[sub + ps];
-      pw0 = (R)sc.w_oms;
-      pw1 = (R)sc.w_tm;
-      pw2 = (R)sc.e_fg;
+    if constexpr (kScalars) {
+      if (pv && pg == 0) {
+        const StateScalars sc = scal[sub + ps];
+        lscal[wv][ps][0] = (R)sc.w_oms;
+        lscal[wv][ps][1] = (R)sc.w_tm;
+        lscal[wv][ps][2] = (R)sc.e_fg;
+      }
     }
+    // pair lanes whose chunk straddles a breakpoint, and states that are invalid
+    const unsigned long long straddle = __ballot(pv && pni > 0 && pi0 != pi1);
+    const unsigned long long invalid = __ballot(pv && pg == 0 && pni == 0);
+    wave_lds_sync();
 
     for (int q = 0; q < nsub; ++q) {
       const int s = sub + q;
-      if (__builtin_amdgcn_readlane(pni, q * G) == 0) {   // invalid state: the finaliser reports it
-        red[wv][lane * SUB + q] = 0.0;
+      if ((invalid >> (q * G)) & 1ull) {   // invalid state: the finaliser reports it
+        red[wv][lane * SUB + q] = (Acc)0;
         continue;
       }
-      const R w_oms = readlane_r(pw0, q * G), w_tm = readlane_r(pw1, q * G), e_fg = readlane_r(pw2, q * G);
+      R w_oms = 0, w_tm = 0, e_fg = 0;
+      if constexpr (kScalars) {
+        w_oms = lscal[wv][q][0];
+        w_tm = lscal[wv][q][1];
+        e_fg = lscal[wv][q][2];
+      }
       R S[NCH][B];
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
@@ -114,18 +151,23 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int pl = q * G + g;
-        const int i0 = __builtin_amdgcn_readlane(pi0, pl);
-        const int i1 = __builtin_amdgcn_readlane(pi1, pl);
         R E[B];
-        if (i0 == i1) {   // the chunk lies in one piece: wave-uniform coefficients
-          const R a = readlane_r(pa, pl), bb = readlane_r(pb, pl), cc = readlane_r(pc, pl),
-                  dd = readlane_r(pd, pl), off = readlane_r(poff, pl);
+        if (!((straddle >> pl) & 1ull)) {   // the chunk lies in one piece: coefficients from LDS
+          const R a = lcoef[wv][pl][0], bb = lcoef[wv][pl][1], cc = lcoef[wv][pl][2], dd = lcoef[wv][pl][3];
+          if constexpr (kLocalPoly) {
 #pragma unroll
-          for (int b = 0; b < B; ++b) {
-            const R tt = xr[b] + off;
-            E[b] = Math<R>::exp2_(a + tt * (bb + tt * (cc + tt * dd)));
+            for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(a + xr[b] * (bb + xr[b] * (cc + xr[b] * dd)));
+          } else {
+            const R off = lcoef[wv][pl][4];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+              const R tt = xr[b] + off;
+              E[b] = Math<R>::exp2_(a + tt * (bb + tt * (cc + tt * dd)));
+            }
           }
         } else {          // a breakpoint falls inside the chunk: evaluate each piece, select per bin
+          const int i0 = __builtin_amdgcn_readlane(pi0, pl);
+          const int i1 = __builtin_amdgcn_readlane(pi1, pl);
           const size_t base = (size_t)(s * G + g) * kMaxKnots;
           R Q[B];
           for (int j = i0; j <= i1; ++j) {
@@ -165,55 +207,48 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
           }
         }
       }
-      R vb[B];
+      // One reciprocal and one logarithm per bin for all channels,
+      //   sum_c ND_c / S_c = num / prod_c S_c,   sum_c w_c ln S_c = ln2 log2(prod_c S_c^w_c)
+      // (w = 2 for the merged A/E row), accumulated along the lane's bins.
+      R v = 0;
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        // One reciprocal and one logarithm per bin for all channels:
-        //   sum_c ND_c / S_c = num / prod_c S_c,   sum_c w_c ln S_c = ln2 log2(prod_c S_c^w_c)
-        // (w = 2 for the merged A/E row).
-        R v;
         if constexpr (NCH == 2) {
           const R P = S[0][b] * S[1][b];
           const R num = ND[1][b] * S[0][b] + ND[0][b] * S[1][b];
-          v = num * Math<R>::rcp_(P) + NL[b] * Math<R>::log2_(P * S[0][b]);
+          v += num * Math<R>::rcp_(P);
+          v += NL[b] * Math<R>::log2_(P * S[0][b]);
         } else {
           const R P01 = S[0][b] * S[1][b];
           const R P = P01 * S[2][b];
           const R num = S[2][b] * (ND[1][b] * S[0][b] + ND[0][b] * S[1][b]) + ND[2][b] * P01;
-          v = num * Math<R>::rcp_(P) + NL[b] * Math<R>::log2_(P);
+          v += num * Math<R>::rcp_(P);
+          v += NL[b] * Math<R>::log2_(P);
         }
-        vb[b] = v;
       }
-      // pairwise sum of the lane's bins, then one double-precision partial per lane
-#pragma unroll
-      for (int w = 1; w < B; w <<= 1)
-#pragma unroll
-        for (int b = 0; b + w < B; b += 2 * w) vb[b] += vb[b + w];
-      double acc = (double)vb[0];
+      Acc acc = (Acc)v;
       if (!isfinite(acc)) {
         // A channel product left the floating-point range (an extreme state):
-        // redo the chunk with one reciprocal and logarithm per channel, so that
-        // only a non-finite or vanishing channel PSD marks the state.
-        acc = 0.0;
+        // redo the lane's bins with one reciprocal and logarithm per channel, so
+        // that only a non-finite or vanishing channel PSD marks the state.
+        R w = 0;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-          R v = 0;
+        for (int b = 0; b < B; ++b)
 #pragma unroll
           for (int c = 0; c < NCH; ++c) {
             const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;
-            v += ND[c][b] * Math<R>::rcp_(S[c][b]) + (lw * NL[b]) * Math<R>::log2_(S[c][b]);
+            w += ND[c][b] * Math<R>::rcp_(S[c][b]) + (lw * NL[b]) * Math<R>::log2_(S[c][b]);
           }
-          acc += (double)v;
-        }
+        acc = (Acc)w;
       }
       red[wv][lane * SUB + q] = acc;
     }
-    // lane q adds the 64 lane partials of state sub + q in a fixed order
+    // lane q adds the 64 lane partials of state sub + q in a fixed order (double)
     wave_lds_sync();
     if (lane < nsub) {
       double sum = 0.0;
 #pragma unroll 8
-      for (int i = 0; i < kWave; ++i) sum += red[wv][i * SUB + lane];
+      for (int i = 0; i < kWave; ++i) sum += (double)red[wv][i * SUB + lane];
       partial[(size_t)(sub + lane) * n_chunks + chunk] = sum;
     }
     wave_lds_sync();
@@ -249,7 +284,8 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
   const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
 #define LPS_FWD(MODE, NCH, FG)                                                                              \
   hipLaunchKernelGGL((k_forward<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,     \
-                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->n_int, ctx->scal,      \
+                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->coef64, ctx->n_int,    \
+                     ctx->scal,                                                                               \
                      ctx->partial)
   const bool fg = L.has_fg != 0;
   if (L.mode == kSplit && L.nch == 2 && !fg) LPS_FWD(kSplit, 2, false);
