@@ -13,14 +13,14 @@
 // knots).  The power law of Eq. (pl) is part of the background group's
 // exponent, so dlogL/du and dlogL/dalpha follow from that group's moments.
 //
-// Three launches after the coefficient kernel:
+// Two launches after the coefficient kernel:
 //   k_grad        per (chunk, state tile): logL partial, template sums and
 //                 first-piece moments per group in one 16/32-value record,
 //                 last-piece moments and interior pieces for chunks that
 //                 straddle a knot;
-//   k_grad_reduce per (state, group): stitches the chunk records into
-//                 per-piece moments in chunk order (deterministic);
-//   k_grad_finish per state: logL, template gradients, Akima backward.
+//   k_grad_finish one wave per state: stitches the chunk records into
+//                 per-piece moments (fixed order, deterministic), then logL,
+//                 template gradients and the Akima backward, lane per knot.
 #include <math.h>
 
 #include "lps_batched.hpp"
@@ -348,196 +348,271 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
   }
 }
 
-// Stitch chunk records into per-piece moments, in chunk order.
-__global__ void k_grad_reduce(int n_states, int G, int NV, int n_chunks, const int32_t* __restrict__ n_int,
-                              const double* __restrict__ rec, const int2* __restrict__ gidx,
-                              const double* __restrict__ glast, double* __restrict__ moments) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n_states * G) return;
-  const int s = id / G, g = id - (id / G) * G;
-  const int n = n_int[s * G + g];
-  if (n == 0) return;
-  double* mo = moments + (size_t)(s * G + g) * kMaxKnots * 4;
-  int cur = 0;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int c = 0; c < n_chunks; ++c) {
-    const size_t ro = (size_t)s * n_chunks + c;
-    const int2 ab = gidx[ro * G + g];
-    const double* first = rec + ro * NV + 4 + 4 * g;
-    if (ab.x > cur) {
-      for (int p = 0; p < 4; ++p) mo[cur * 4 + p] = acc[p];
-      for (int j = cur + 1; j < ab.x; ++j)
-        for (int p = 0; p < 4; ++p) mo[j * 4 + p] = 0.0;   // no bin falls in piece j
-      cur = ab.x;
-      for (int p = 0; p < 4; ++p) acc[p] = 0.0;
-    }
-    for (int p = 0; p < 4; ++p) acc[p] += first[p];
-    if (ab.y > ab.x) {
-      for (int p = 0; p < 4; ++p) mo[cur * 4 + p] = acc[p];
-      cur = ab.y;
-      const double* last = glast + (ro * G + g) * 4;
-      for (int p = 0; p < 4; ++p) acc[p] = last[p];
-    }
+// Per-wave LDS of the finishing kernel.
+struct FinishLds {
+  double mo[kMaxGroups][kMaxKnots][4];   // per-piece moments M^p_i of every group
+  double m[kMaxKnots], h[kMaxKnots], s[kMaxKnots], w[kMaxKnots];
+  double sbn[kMaxKnots], sb[kMaxKnots], pl[kMaxKnots], pr[kMaxKnots], cr[kMaxKnots], cl[kMaxKnots];
+  double wbs[kMaxKnots], q[kMaxKnots], hb[kMaxKnots];
+};
+
+__device__ inline uint64_t wave_or64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, kWave);
+    v |= ((uint64_t)hi << 32) | lo;
   }
-  for (int p = 0; p < 4; ++p) mo[cur * 4 + p] = acc[p];
-  for (int j = cur + 1; j < n; ++j)
-    for (int p = 0; p < 4; ++p) mo[j * 4 + p] = 0.0;
+  return v;
 }
 
-// Backward through the spline construction of App. A for one spline:
-// given Mbar[i][p] (moments of dlogL/dP over piece i, already times ln 10)
-// accumulate dlogL/dy_i and dlogL/dx_i (edges excluded).
-__device__ void spline_backward(const double* __restrict__ x, const double* __restrict__ y, int n,
-                                const double* __restrict__ mom, double* __restrict__ dy, double* __restrict__ dx) {
-  double m[kMaxKnots], h[kMaxKnots], s[kMaxKnots], w[kMaxKnots];
-  double mb[kMaxKnots], hb[kMaxKnots], sb[kMaxKnots], wb[kMaxKnots], yb[kMaxKnots], xb[kMaxKnots];
-  for (int i = 0; i < n; ++i) {
-    yb[i] = 0.0;
-    xb[i] = 0.0;
-    sb[i] = 0.0;
-  }
-  for (int i = 0; i + 1 < n; ++i) {
-    h[i] = x[i + 1] - x[i];
-    m[i] = (y[i + 1] - y[i]) / h[i];
-    mb[i] = 0.0;
-    hb[i] = 0.0;
-  }
-  const bool akima = n >= 4;
-  if (akima) {
-    for (int i = 0; i + 2 < n; ++i) {
-      w[i] = fabs(m[i + 1] - m[i]);
-      wb[i] = 0.0;
+// Per-piece moments of group g of state s from the chunk records.  Piece i
+// collects the last-piece moments of the chunk that straddles into it (if
+// any) followed by the first-piece moments of every chunk that starts in it,
+// in chunk order; pieces lying strictly inside a straddling chunk were
+// written to `moments` by k_grad.  Lanes walk 64 chunks at a time; a
+// segmented scan keyed by the starting piece sums the chunks of one piece,
+// so the order of every sum is fixed.
+__device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks, int ni,
+                             const double* __restrict__ rec, const int2* __restrict__ gidx,
+                             const double* __restrict__ glast, const double* __restrict__ moments,
+                             double (*mo)[4]) {
+  for (int p = 0; p < 4; ++p) mo[lane][p] = 0.0;
+  uint64_t inner = 0;
+  wave_lds_sync();
+  for (int cb = 0; cb < n_chunks; cb += kWave) {
+    const int c = cb + lane;
+    const bool have = c < n_chunks;
+    const size_t ro = (size_t)s * n_chunks + (have ? c : 0);
+    const int2 ab = have ? gidx[ro * G + g] : make_int2(-1, -1);
+    double v[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) v[p] = have ? rec[ro * NV + 4 + 4 * g + p] : 0.0;
+    if (ab.y > ab.x) {
+      const double* last = glast + (ro * G + g) * 4;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) mo[ab.y][p] += last[p];
+      if (ab.y - ab.x >= 2) inner |= ((1ull << ab.y) - 1ull) & ~((1ull << (ab.x + 1)) - 1ull);
     }
-    s[0] = 0.5 * (3.0 * m[0] - m[1]);
-    s[n - 1] = 0.5 * (3.0 * m[n - 2] - m[n - 3]);
-    for (int i = 1; i <= n - 2; ++i) {
-      const int ir = i < n - 2 ? i : n - 3;
-      const int il = i - 2 > 0 ? i - 2 : 0;
-      s[i] = akima_avg(w[ir], m[i - 1], w[il], m[i]);
-    }
-  } else {
-    for (int i = 0; i + 1 < n; ++i) s[i] = m[i];
-  }
-  // pieces: a = y_i, b = s_i (or m_i), c, d; P = a + b t + c t^2 + d t^3, t = x - x_i
-  for (int i = 0; i + 1 < n; ++i) {
-    const double M0 = mom[i * 4 + 0], M1 = mom[i * 4 + 1], M2 = mom[i * 4 + 2], M3 = mom[i * 4 + 3];
-    if (akima) {
-      const double hi = h[i];
-      const double c = (3.0 * m[i] - 2.0 * s[i] - s[i + 1]) / hi;
-      const double d = (s[i] + s[i + 1] - 2.0 * m[i]) / (hi * hi);
-      yb[i] += M0;
-      sb[i] += M1;
-      xb[i] -= s[i] * M0 + 2.0 * c * M1 + 3.0 * d * M2;      // t depends on x_i
-      // c = (3 m - 2 s_i - s_{i+1}) / h
-      mb[i] += 3.0 * M2 / hi;
-      sb[i] -= 2.0 * M2 / hi;
-      sb[i + 1] -= M2 / hi;
-      hb[i] -= M2 * c / hi;
-      // d = (s_i + s_{i+1} - 2 m) / h^2
-      const double h2 = hi * hi;
-      sb[i] += M3 / h2;
-      sb[i + 1] += M3 / h2;
-      mb[i] -= 2.0 * M3 / h2;
-      hb[i] -= 2.0 * M3 * d / hi;
-    } else {
-      yb[i] += M0;
-      mb[i] += M1;
-      xb[i] -= m[i] * M0;
-    }
-  }
-  if (akima) {
-    // knot slopes
-    mb[0] += 1.5 * sb[0];
-    mb[1] -= 0.5 * sb[0];
-    mb[n - 2] += 1.5 * sb[n - 1];
-    mb[n - 3] -= 0.5 * sb[n - 1];
-    for (int i = 1; i <= n - 2; ++i) {
-      const int ir = i < n - 2 ? i : n - 3;
-      const int il = i - 2 > 0 ? i - 2 : 0;
-      const double wr = w[ir], wl = w[il], den = wr + wl;
-      if (den == 0.0) {
-        mb[i - 1] += 0.5 * sb[i];
-        mb[i] += 0.5 * sb[i];
-      } else {
-        mb[i - 1] += sb[i] * wr / den;
-        mb[i] += sb[i] * wl / den;
-        wb[ir] += sb[i] * (m[i - 1] - s[i]) / den;
-        wb[il] += sb[i] * (m[i] - s[i]) / den;
+    const int key = ab.x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int ku = __shfl_up(key, d, kWave);
+      double vu[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) vu[p] = __shfl_up(v[p], d, kWave);
+      if (lane >= d && ku == key) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) v[p] += vu[p];
       }
     }
-    // slope weights w_i = |m_{i+1} - m_i| (derivative 0 at 0)
-    for (int i = 0; i + 2 < n; ++i) {
-      const double dlt = m[i + 1] - m[i];
-      const double sg = dlt > 0.0 ? 1.0 : (dlt < 0.0 ? -1.0 : 0.0);
-      mb[i + 1] += wb[i] * sg;
-      mb[i] -= wb[i] * sg;
+    const int kn = __shfl_down(key, 1, kWave);
+    const bool seg_end = have && (lane == kWave - 1 || kn != key);
+    wave_lds_sync();
+    if (seg_end) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) mo[key][p] += v[p];
     }
+    wave_lds_sync();
   }
-  // segment slopes m_i = (y_{i+1} - y_i) / h_i
-  for (int i = 0; i + 1 < n; ++i) {
-    yb[i + 1] += mb[i] / h[i];
-    yb[i] -= mb[i] / h[i];
-    hb[i] -= mb[i] * m[i] / h[i];
+  inner = wave_or64(inner);
+  if (lane < ni && ((inner >> lane) & 1ull)) {
+    const double* src = moments + ((size_t)(s * G + g) * kMaxKnots + lane) * 4;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) mo[lane][p] = src[p];
   }
-  for (int i = 0; i + 1 < n; ++i) {
-    xb[i + 1] += hb[i];
-    xb[i] -= hb[i];
-  }
-  for (int i = 0; i < n; ++i) {
-    dy[i] = yb[i];
-    dx[i] = (i == 0 || i == n - 1) ? 0.0 : xb[i];
-  }
+  wave_lds_sync();
 }
 
-__global__ void k_grad_finish(int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay,
-                              double x_knee, const double* __restrict__ params, const int32_t* __restrict__ off,
-                              const int32_t* __restrict__ kcnt, const double* __restrict__ kx, const double* __restrict__ ky,
-                              const int32_t* __restrict__ n_int, const double* __restrict__ bx,
-                              const double* __restrict__ rec, const double* __restrict__ moments,
-                              const double* __restrict__ c0, const uint32_t* __restrict__ status_ws,
-                              double* __restrict__ logL, double* __restrict__ dparams, double* __restrict__ dkx,
-                              double* __restrict__ dky, uint32_t* __restrict__ status) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Backward through the spline construction of App. A for one spline of n
+// knots, one lane per knot (and per piece: piece i spans knots i, i+1).
+// M0..M3 are the moments of dlogL/dP over the lane's piece (already times
+// ln 10).  Forward quantities: h_i, m_i (segments), w_i = |m_{i+1} - m_i|,
+// knot slopes s_i; pieces a = y_i, b = s_i, c, d.  Every scatter of the
+// sequential adjoint becomes a gather of fixed neighbours through LDS.
+__device__ void spline_backward_wave(int lane, const double* __restrict__ x, const double* __restrict__ y, int n,
+                                     const double (&M)[4], double* __restrict__ dy, double* __restrict__ dx,
+                                     FinishLds& L) {
+  const int i = lane;
+  const bool knot = i < n, seg = i + 1 < n;
+  const double xi = knot ? x[i] : 0.0;
+  const double yi = knot ? y[i] : 0.0;
+  double hi = 1.0, mi = 0.0;
+  if (seg) {
+    hi = x[i + 1] - xi;
+    mi = (y[i + 1] - yi) / hi;
+  }
+  L.m[i] = mi;
+  L.h[i] = hi;
+  wave_lds_sync();
+  const bool akima = n >= 4;
+  double si = mi;
+  if (akima) {
+    if (i + 2 < n) L.w[i] = fabs(L.m[i + 1] - mi);
+    wave_lds_sync();
+    if (i == 0) si = 0.5 * (3.0 * L.m[0] - L.m[1]);
+    else if (i == n - 1) si = 0.5 * (3.0 * L.m[n - 2] - L.m[n - 3]);
+    else if (i < n - 1) {
+      const int ir = i < n - 2 ? i : n - 3;
+      const int il = i - 2 > 0 ? i - 2 : 0;
+      si = akima_avg(L.w[ir], L.m[i - 1], L.w[il], mi);
+    }
+    L.s[i] = si;
+    wave_lds_sync();
+  }
+  // pieces -> (y, s, m, h, x)
+  double yb = 0.0, xb = 0.0, sbo = 0.0, sbn = 0.0, mb = 0.0, hb = 0.0;
+  if (seg) {
+    if (akima) {
+      const double s1 = L.s[i + 1];
+      const double h2 = hi * hi;
+      const double c = (3.0 * mi - 2.0 * si - s1) / hi;
+      const double d = (si + s1 - 2.0 * mi) / h2;
+      yb = M[0];
+      xb = -(si * M[0] + 2.0 * c * M[1] + 3.0 * d * M[2]);   // t = x - x_i
+      sbo = M[1] - 2.0 * M[2] / hi + M[3] / h2;
+      sbn = -M[2] / hi + M[3] / h2;
+      mb = 3.0 * M[2] / hi - 2.0 * M[3] / h2;
+      hb = -M[2] * c / hi - 2.0 * M[3] * d / hi;
+    } else {
+      yb = M[0];
+      mb = M[1];
+      xb = -mi * M[0];
+    }
+  }
+  if (akima) {
+    L.sbn[i] = sbn;
+    wave_lds_sync();
+    const double sbi = knot ? sbo + (i >= 1 ? L.sbn[i - 1] : 0.0) : 0.0;
+    // knot slopes -> (m, w)
+    double pl = 0.0, pr = 0.0, cr = 0.0, cl = 0.0;
+    if (i >= 1 && i <= n - 2) {
+      const int ir = i < n - 2 ? i : n - 3;
+      const int il = i - 2 > 0 ? i - 2 : 0;
+      const double wr = L.w[ir], wl = L.w[il], den = wr + wl;
+      if (den == 0.0) {
+        pl = 0.5 * sbi;
+        pr = 0.5 * sbi;
+      } else {
+        pl = sbi * wr / den;
+        pr = sbi * wl / den;
+        cr = sbi * (L.m[i - 1] - si) / den;
+        cl = sbi * (mi - si) / den;
+      }
+    }
+    L.sb[i] = sbi;
+    L.pl[i] = pl;
+    L.pr[i] = pr;
+    L.cr[i] = cr;
+    L.cl[i] = cl;
+    wave_lds_sync();
+    // segment k = i gathers the knot-slope terms aimed at m_k
+    if (seg) {
+      if (i >= 1 && i <= n - 2) mb += L.pr[i];
+      if (i + 1 <= n - 2) mb += L.pl[i + 1];
+      if (i == 0) mb += 1.5 * L.sb[0];
+      if (i == 1) mb -= 0.5 * L.sb[0];
+      if (i == n - 2) mb += 1.5 * L.sb[n - 1];
+      if (i == n - 3) mb -= 0.5 * L.sb[n - 1];
+    }
+    // slope weight k = i gathers the terms aimed at w_k (clamped stencils at both ends)
+    double ws = 0.0;
+    if (i <= n - 3) {
+      double wb = 0.0;
+      if (i >= 1) wb += L.cr[i];
+      if (i == n - 3) wb += L.cr[n - 2];
+      if (i + 2 <= n - 2) wb += L.cl[i + 2];
+      if (i == 0) wb += L.cl[1];
+      const double dlt = L.m[i + 1] - mi;
+      const double sg = dlt > 0.0 ? 1.0 : (dlt < 0.0 ? -1.0 : 0.0);
+      ws = wb * sg;
+    }
+    L.wbs[i] = ws;
+    wave_lds_sync();
+    if (seg) mb += (i >= 1 ? L.wbs[i - 1] : 0.0) - ws;
+  }
+  // segment slopes m_i = (y_{i+1} - y_i) / h_i and widths h_i = x_{i+1} - x_i
+  double q = 0.0;
+  if (seg) {
+    q = mb / hi;
+    hb -= mb * mi / hi;
+  } else {
+    hb = 0.0;
+  }
+  L.q[i] = q;
+  L.hb[i] = hb;
+  wave_lds_sync();
+  if (knot) {
+    yb += (i >= 1 ? L.q[i - 1] : 0.0) - q;
+    xb += (i >= 1 ? L.hb[i - 1] : 0.0) - hb;
+    dy[i] = yb;
+    dx[i] = (i == 0 || i == n - 1) ? 0.0 : xb;
+  }
+  wave_lds_sync();
+}
+
+// One wave per state: stitches the chunk records into per-piece moments,
+// then forms logL, the template-parameter gradients and the knot gradients.
+__global__ __launch_bounds__(256) void k_grad_finish(
+    int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay, double x_knee,
+    const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+    const double* __restrict__ kx, const double* __restrict__ ky, const int32_t* __restrict__ n_int,
+    const double* __restrict__ bx, const double* __restrict__ rec, const int2* __restrict__ gidx,
+    const double* __restrict__ glast, const double* __restrict__ moments, const double* __restrict__ c0,
+    const uint32_t* __restrict__ status_ws, double* __restrict__ logL, double* __restrict__ dparams,
+    double* __restrict__ dkx, double* __restrict__ dky, uint32_t* __restrict__ status) {
+  __shared__ FinishLds lds[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = uniform(threadIdx.x >> 6);
+  const int s = uniform(blockIdx.x * kWavesPerBlock + wv);
   if (s >= n_states) return;
+  FinishLds& L = lds[wv];
   const int G = lay.n_grp;
   uint32_t st = status_ws[s];
   double sums[4] = {0.0, 0.0, 0.0, 0.0};
   if (st == 0) {
-    for (int c = 0; c < n_chunks; ++c) {
+    for (int c = lane; c < n_chunks; c += kWave) {
       const double* r = rec + ((size_t)s * n_chunks + c) * NV;
+#pragma unroll
       for (int i = 0; i < 4; ++i) sums[i] += r[i];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sums[i] = wave_sum(sums[i]);
   }
-  const double L = c0[0] - sums[0];
-  if (st == 0 && !isfinite(L)) st |= LPS_ST_PSD;
-  if (status) status[s] = st;
+  const double Lv = c0[0] - sums[0];
+  if (st == 0 && !isfinite(Lv)) st |= LPS_ST_PSD;
+  if (lane == 0) {
+    if (status) status[s] = st;
+    logL[s] = st ? -INFINITY : Lv;
+  }
   if (st) {
-    logL[s] = -INFINITY;
-    for (int p = 0; p < n_params; ++p) dparams[p * (size_t)n_states + s] = 0.0;
+    if (lane < n_params) dparams[lane * (size_t)n_states + s] = 0.0;
     for (int j = 0; j < n_spl; ++j) {
       int a, cn;
       knot_range(off, kcnt, s * n_spl + j, a, cn);
-      for (int i = a; a >= 0 && i < a + cn; ++i) {
-        dkx[i] = 0.0;
-        dky[i] = 0.0;
+      if (a < 0) continue;
+      for (int i = lane; i < cn; i += kWave) {
+        dkx[a + i] = 0.0;
+        dky[a + i] = 0.0;
       }
     }
     return;
   }
-  logL[s] = L;
+  for (int g = 0; g < G; ++g)
+    stitch_group(lane, s, g, G, NV, n_chunks, n_int[s * G + g], rec, gidx, glast, moments, L.mo[g]);
   const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
   const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
   double r_oms = sums[1], r_tm = sums[2];
   double du = 0.0, dalpha = 0.0;
   for (int g = 0; g < G; ++g) {
     const int ni = n_int[s * G + g];
-    const double* mo = moments + (size_t)(s * G + g) * kMaxKnots * 4;
-    const double* bxs = bx + (size_t)(s * G + g) * kMaxKnots;
     double m0 = 0.0, m1x = 0.0;
-    for (int i = 0; i < ni; ++i) {
-      m0 += mo[i * 4 + 0];
-      m1x += mo[i * 4 + 1] + (bxs[i] - x_knee) * mo[i * 4 + 0];
+    if (lane < ni) {
+      const double b = bx[(size_t)(s * G + g) * kMaxKnots + lane];
+      m0 = L.mo[g][lane][0];
+      m1x = L.mo[g][lane][1] + (b - x_knee) * m0;
     }
+    m0 = wave_sum(m0);
+    m1x = wave_sum(m1x);
     switch (lay.grp_kind[g]) {
       case kGOms: r_oms = m0; break;
       case kGTm: r_tm = m0; break;
@@ -548,24 +623,27 @@ __global__ void k_grad_finish(int n_states, int n_spl, int n_params, int NV, int
       default: break;
     }
   }
-  dparams[LPS_P_AOMS * (size_t)n_states + s] = 2.0 * r_oms / a_oms;
-  dparams[LPS_P_ATM * (size_t)n_states + s] = 2.0 * r_tm / a_tm;
-  dparams[LPS_P_U * (size_t)n_states + s] = du;
-  dparams[LPS_P_ALPHA * (size_t)n_states + s] = dalpha;
-  if (n_params > 4) dparams[LPS_P_UFG * (size_t)n_states + s] = kLn10 * sums[3];
-  // spline knots: sum the moments of every group fed by the spline
-  double mom[kMaxKnots * 4];
+  if (lane == 0) {
+    dparams[LPS_P_AOMS * (size_t)n_states + s] = 2.0 * r_oms / a_oms;
+    dparams[LPS_P_ATM * (size_t)n_states + s] = 2.0 * r_tm / a_tm;
+    dparams[LPS_P_U * (size_t)n_states + s] = du;
+    dparams[LPS_P_ALPHA * (size_t)n_states + s] = dalpha;
+    if (n_params > 4) dparams[LPS_P_UFG * (size_t)n_states + s] = kLn10 * sums[3];
+  }
+  // spline knots: the moments of every group fed by the spline, summed in group order
   for (int j = 0; j < n_spl; ++j) {
     int a, n;
     knot_range(off, kcnt, s * n_spl + j, a, n);
     if (n == 0) continue;
-    for (int i = 0; i < (n - 1) * 4; ++i) mom[i] = 0.0;
-    for (int g = 0; g < G; ++g) {
-      if (lay.grp_spline[g] != j) continue;
-      const double* mo = moments + (size_t)(s * G + g) * kMaxKnots * 4;
-      for (int i = 0; i < (n - 1) * 4; ++i) mom[i] += kLn10 * mo[i];
+    double M[4] = {0.0, 0.0, 0.0, 0.0};
+    if (lane + 1 < n) {
+      for (int g = 0; g < G; ++g) {
+        if (lay.grp_spline[g] != j) continue;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) M[p] += kLn10 * L.mo[g][lane][p];
+      }
     }
-    spline_backward(kx + a, ky + a, n, mom, dky + a, dkx + a);
+    spline_backward_wave(lane, kx + a, ky + a, n, M, dky + a, dkx + a, L);
   }
 }
 
@@ -639,12 +717,10 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
                                         gidx, glast, s);
   if (e != hipSuccess) return e;
   timing_end(ctx, s);
-  hipLaunchKernelGGL(k_grad_reduce, dim3((n * G + 127) / 128), dim3(128), 0, s, n, G, NV, n_chunks, ctx->n_int, rec,
-                     gidx, glast, ctx->moments);
-  hipLaunchKernelGGL(k_grad_finish, dim3((n + 63) / 64), dim3(64), 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
-                     ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
-                     ctx->n_int,
-                     ctx->bx, rec, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams, dkx, dky, status);
+  hipLaunchKernelGGL(k_grad_finish, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kWave * kWavesPerBlock), 0,
+                     s, n, ctx->n_spl, ctx->n_params, NV, n_chunks, ctx->lay, log10(ctx->f_knee), st->params,
+                     st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->n_int, ctx->bx, rec, gidx, glast,
+                     ctx->moments, ctx->c0, ctx->status_ws, logL, dparams, dkx, dky, status);
   return hipGetLastError();
 }
 

@@ -57,3 +57,47 @@ __device__ inline uint32_t validate_state(int s, int n_states, int n_spl, int k_
 }
 
 }  // namespace lps
+
+namespace lps {
+
+__device__ inline uint32_t wave_or(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v |= (uint32_t)__shfl_xor((int)v, o, 64);
+  return v;
+}
+
+// The same checks as validate_state, made by one wave with a lane per knot
+// (k_max <= 64).  Every lane of the wave must call it with the same state;
+// every lane receives the state's status bits.
+__device__ inline uint32_t validate_state_wave(int lane, int s, int n_states, int n_spl, int k_max, int n_params,
+                                               const double* __restrict__ params, const int32_t* __restrict__ off,
+                                               const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
+                                               const double* __restrict__ ky, double x_first, double x_last) {
+  uint32_t st = 0;
+  if (lane < n_params && !isfinite(params[lane * (size_t)n_states + s])) st |= LPS_ST_NONFINITE;
+  if (lane == 0) {
+    const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
+    const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
+    if (!(a_oms > 0.0 && a_tm > 0.0)) st |= LPS_ST_AMPLITUDE;
+  }
+  for (int j = 0; j < n_spl; ++j) {
+    int a, cnt;
+    knot_range(off, kcnt, s * n_spl + j, a, cnt);
+    if (cnt == 0) continue;
+    if (a < 0 || cnt < 0 || cnt == 1 || cnt > k_max) {
+      if (lane == 0) st |= LPS_ST_COUNT;
+      continue;
+    }
+    const bool mine = lane < cnt;
+    const double xi = mine ? kx[a + lane] : 0.0;
+    const bool bad = mine && !(isfinite(xi) && isfinite(ky[a + lane]));
+    if (__ballot(bad) != 0ull) {
+      if (lane == 0) st |= LPS_ST_NONFINITE;
+      continue;
+    }
+    if (lane + 1 < cnt && !(kx[a + lane + 1] > xi)) st |= LPS_ST_ORDER;
+    if (lane == 0 && (xi > x_first + kCoverSlack || kx[a + cnt - 1] < x_last - kCoverSlack)) st |= LPS_ST_COVER;
+  }
+  return wave_or(st);
+}
+
+}  // namespace lps
