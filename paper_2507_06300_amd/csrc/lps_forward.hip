@@ -48,7 +48,12 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   // (a, b, c, d, offset), the per-state scalars, and the per-state lane
   // partials stored transposed (red[source lane][state]).
   using Acc = typename std::conditional<kMixed, float, double>::type;
-  __shared__ R lcoef[kWavesPerBlock][kWave][5];
+  using R4 = typename std::conditional<kMixed, float4, double4>::type;
+  __shared__ R4 lcoef[kWavesPerBlock][kWave];
+  __shared__ R loff[kWavesPerBlock][kWave];
+  __shared__ R4 lcoef2[kWavesPerBlock][kWave];   // next piece of a chunk that crosses one breakpoint
+  __shared__ R loff2[kWavesPerBlock][kWave];
+  __shared__ R llim[kWavesPerBlock][kWave];
   __shared__ R lscal[kWavesPerBlock][SUB][4];
   __shared__ Acc red[kWavesPerBlock][kWave * SUB];
   const int lane = threadIdx.x & (kWave - 1);
@@ -94,29 +99,45 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     int pi0 = 0, pi1 = 0;
     if (pni > 0) {
       pi0 = count_le(bx + pbase, pni, xf);
-      pi1 = count_le(bx + pbase, pni, xl);
-      const double b0 = bx[pbase + pi0];
-      R rec[5];
-      if constexpr (kLocalPoly) {
-        // Q(x) = a + b t + c t^2 + d t^3, t = x - b0 = t0 + dx  ->  polynomial in dx = x - xo
-        const double* cf = coef64 + (pbase + pi0) * 4;
-        const double t0 = xo - b0;
-        const double a = cf[0], b = cf[1], c = cf[2], d = cf[3];
-        rec[0] = (R)(a + t0 * (b + t0 * (c + t0 * d)));
-        rec[1] = (R)(b + t0 * (2.0 * c + 3.0 * d * t0));
-        rec[2] = (R)(c + 3.0 * d * t0);
-        rec[3] = (R)d;
-        rec[4] = 0;
-      } else {
-        const R* cf = coef + (pbase + pi0) * 4;
-        rec[0] = cf[0];
-        rec[1] = cf[1];
-        rec[2] = cf[2];
-        rec[3] = cf[3];
-        rec[4] = kMixed ? (R)(xo - b0) : (R)(-b0);
+      // the chunk usually ends in the piece it starts in: one more breakpoint
+      // decides, and only a crossing chunk searches for its last piece
+      const double b_next = pi0 + 1 < pni ? bx[pbase + pi0 + 1] : (double)INFINITY;
+      pi1 = b_next <= xl ? count_le(bx + pbase, pni, xl) : pi0;
+      // record of piece i (breakpoint bi): cubic coefficients and abscissa offset
+      auto piece_rec = [&](int i, double bi, R4& r4, R& off) {
+        if constexpr (kLocalPoly) {
+          // Q(x) = a + b t + c t^2 + d t^3, t = x - bi = t0 + dx  ->  polynomial in dx = x - xo
+          const double* cf = coef64 + (pbase + i) * 4;
+          const double t0 = xo - bi;
+          const double a = cf[0], b = cf[1], c = cf[2], d = cf[3];
+          r4.x = (R)(a + t0 * (b + t0 * (c + t0 * d)));
+          r4.y = (R)(b + t0 * (2.0 * c + 3.0 * d * t0));
+          r4.z = (R)(c + 3.0 * d * t0);
+          r4.w = (R)d;
+          off = 0;
+        } else {
+          const R* cf = coef + (pbase + i) * 4;
+          r4.x = cf[0];
+          r4.y = cf[1];
+          r4.z = cf[2];
+          r4.w = cf[3];
+          off = kMixed ? (R)(xo - bi) : (R)(-bi);
+        }
+      };
+      R4 r4;
+      R off;
+      piece_rec(pi0, bx[pbase + pi0], r4, off);
+      lcoef[wv][lane] = r4;
+      if constexpr (!kLocalPoly) loff[wv][lane] = off;
+      if (pi1 > pi0) {
+        // the chunk crosses breakpoint pi0 + 1: stage the next piece as well,
+        // with the abscissa (in the table's units) where it takes over
+        const double b1 = b_next;
+        piece_rec(pi0 + 1, b1, r4, off);
+        lcoef2[wv][lane] = r4;
+        if constexpr (!kLocalPoly) loff2[wv][lane] = off;
+        llim[wv][lane] = kMixed ? (R)(b1 - xo) : (R)b1;
       }
-#pragma unroll
-      for (int i = 0; i < 5; ++i) lcoef[wv][lane][i] = rec[i];
     }
     if constexpr (kScalars) {
       if (pv && pg == 0) {
@@ -128,6 +149,11 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     }
     // pair lanes whose chunk straddles a breakpoint, and states that are invalid
     const unsigned long long straddle = __ballot(pv && pni > 0 && pi0 != pi1);
+    const unsigned long long multi = __ballot(pv && pni > 0 && pi1 > pi0 + 1);
+    // bit q*G set when any group of state q crosses a breakpoint in this chunk
+    unsigned long long cross_state = straddle;
+#pragma unroll
+    for (int g = 1; g < G; ++g) cross_state |= straddle >> g;
     const unsigned long long invalid = __ballot(pv && pg == 0 && pni == 0);
     wave_lds_sync();
 
@@ -148,45 +174,23 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       for (int c = 0; c < NCH; ++c)
 #pragma unroll
         for (int b = 0; b < B; ++b) S[c][b] = FG ? Kt[3][c][b] * e_fg : (R)0;
+      // E = 2^Q of the piece staged for pair pl, for the lane's bins
+      auto uniform_E = [&](int pl, R(&E)[B]) {
+        const R4 c0 = lcoef[wv][pl];
+        if constexpr (kLocalPoly) {
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int pl = q * G + g;
-        R E[B];
-        if (!((straddle >> pl) & 1ull)) {   // the chunk lies in one piece: coefficients from LDS
-          const R a = lcoef[wv][pl][0], bb = lcoef[wv][pl][1], cc = lcoef[wv][pl][2], dd = lcoef[wv][pl][3];
-          if constexpr (kLocalPoly) {
+          for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(c0.x + xr[b] * (c0.y + xr[b] * (c0.z + xr[b] * c0.w)));
+        } else {
+          const R off = loff[wv][pl];
 #pragma unroll
-            for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(a + xr[b] * (bb + xr[b] * (cc + xr[b] * dd)));
-          } else {
-            const R off = lcoef[wv][pl][4];
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-              const R tt = xr[b] + off;
-              E[b] = Math<R>::exp2_(a + tt * (bb + tt * (cc + tt * dd)));
-            }
+          for (int b = 0; b < B; ++b) {
+            const R tt = xr[b] + off;
+            E[b] = Math<R>::exp2_(c0.x + tt * (c0.y + tt * (c0.z + tt * c0.w)));
           }
-        } else {          // a breakpoint falls inside the chunk: evaluate each piece, select per bin
-          const int i0 = __builtin_amdgcn_readlane(pi0, pl);
-          const int i1 = __builtin_amdgcn_readlane(pi1, pl);
-          const size_t base = (size_t)(s * G + g) * kMaxKnots;
-          R Q[B];
-          for (int j = i0; j <= i1; ++j) {
-            const R* cf = coef + (base + j) * 4;
-            const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
-            const double bj = bx[base + j];
-            const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
-            const R lim = kMixed ? (R)(bj - xo) : (R)bj;   // bin is in piece j when xr >= lim
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-              const R tt = xr[b] + off;
-              const R qv = a + tt * (bb + tt * (cc + tt * dd));
-              Q[b] = (j == i0 || xr[b] >= lim) ? qv : Q[b];
-            }
-          }
-#pragma unroll
-          for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(Q[b]);
         }
-        // fold this group's factor into the channel PSDs
+      };
+      // fold group g's factor into the channel PSDs
+      auto fold = [&](int g, const R(&E)[B]) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           if constexpr (MODE == kSplit) {
@@ -205,6 +209,62 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
               for (int c = 0; c < NCH; ++c) S[c][b] += Kt[2][c][b] * E[b];
             }
           }
+        }
+      };
+      if (!((cross_state >> (q * G)) & 1ull)) {
+        // the usual case: the chunk lies inside one piece of every group, so
+        // the state's body is straight-line code
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          R E[B];
+          uniform_E(q * G + g, E);
+          fold(g, E);
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int pl = q * G + g;
+          const bool str = (straddle >> pl) & 1ull;
+          const bool mul = (multi >> pl) & 1ull;
+          R Q[B];
+          if (mul) {   // several breakpoints inside the chunk: each piece from memory, select per bin
+            const int i0 = __builtin_amdgcn_readlane(pi0, pl);
+            const int i1 = __builtin_amdgcn_readlane(pi1, pl);
+            const size_t base = (size_t)(s * G + g) * kMaxKnots;
+            for (int j = i0; j <= i1; ++j) {
+              const R* cf = coef + (base + j) * 4;
+              const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
+              const double bj = bx[base + j];
+              const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
+              const R lim = kMixed ? (R)(bj - xo) : (R)bj;   // bin is in piece j when xr >= lim
+#pragma unroll
+              for (int b = 0; b < B; ++b) {
+                const R tt = xr[b] + off;
+                const R qv = a + tt * (bb + tt * (cc + tt * dd));
+                Q[b] = (j == i0 || xr[b] >= lim) ? qv : Q[b];
+              }
+            }
+          } else {     // at most one breakpoint: both staged pieces from LDS, select per bin
+            const R4 c0 = lcoef[wv][pl];
+            const R4 c1 = lcoef2[wv][pl];
+            const R lim = str ? llim[wv][pl] : (R)INFINITY;
+            R o0 = 0, o1 = 0;
+            if constexpr (!kLocalPoly) {
+              o0 = loff[wv][pl];
+              o1 = loff2[wv][pl];
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+              const bool second = xr[b] >= lim;
+              const R4 cc = second ? c1 : c0;
+              const R t = xr[b] + (second ? o1 : o0);
+              Q[b] = cc.x + t * (cc.y + t * (cc.z + t * cc.w));
+            }
+          }
+          R E[B];
+#pragma unroll
+          for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(Q[b]);
+          fold(g, E);
         }
       }
       // One reciprocal and one logarithm per bin for all channels,
