@@ -135,7 +135,9 @@ typedef struct {
  */
 lps_status lps_create(const lps_dataset_desc* desc /*[host]*/, int device, lps_ctx** out /*[host]*/);
 
-/* Free a context and all of its device memory (NULL is a no-op). */
+/* Free a context and all of its device memory (NULL is a no-op).  It
+ * synchronises the device and frees memory, so it must not be called while
+ * any stream of the process is being captured into a graph. */
 lps_status lps_destroy(lps_ctx* ctx);
 
 /*
@@ -236,6 +238,8 @@ typedef struct {
 
 /* Allocate chain storage for n_walkers * n_temps chains (<= max_grad_states of ctx). */
 lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* desc /*[host]*/, lps_sampler** out /*[host]*/);
+/* Free a sampler (NULL is a no-op); the context must still exist.  Like
+ * lps_destroy it synchronises and frees device memory: not during a capture. */
 lps_status lps_sampler_destroy(lps_sampler* sm);
 
 /* Load the chains from a packed-CSR batch (n_states = chains, every spline with
@@ -267,6 +271,11 @@ lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags /*[h
 
 /* Static text for a status code. */
 const char* lps_strerror(lps_status s);
+
+/* The HIP error behind the most recent LPS_E_DEVICE returned on the calling
+ * host thread (0 = none yet); *name, if name is not NULL, receives its static
+ * HIP error name. */
+int32_t lps_last_device_error(const char** name /*[host]*/);
 
 /* Number of bins per wave chunk used by the batched kernels (for sizing checks). */
 int32_t lps_chunk_bins(lps_precision prec);

@@ -31,9 +31,10 @@ _STATUS_NAMES = {0: "LPS_OK", 1: "LPS_E_NULL", 2: "LPS_E_SHAPE", 3: "LPS_E_CAPAC
 
 
 class LpsError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, detail=None):
         self.code = code
-        super().__init__(f"{where}: {_STATUS_NAMES.get(code, code)} ({lib().lps_strerror(code).decode()})")
+        msg = f"{where}: {_STATUS_NAMES.get(code, code)} ({lib().lps_strerror(code).decode()})"
+        super().__init__(msg + (f": {detail}" if detail else ""))
 
 
 class _Desc(ctypes.Structure):
@@ -57,7 +58,7 @@ class _States(ctypes.Structure):
 
 SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
            "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error", "lps_strerror",
-           "lps_chunk_bins", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune",
+           "lps_chunk_bins", "lps_last_device_error", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune",
            "lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
            "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10"]
 
@@ -84,6 +85,8 @@ def lib():
     L.lps_get_error.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
     L.lps_strerror.argtypes = [ctypes.c_int]
     L.lps_strerror.restype = ctypes.c_char_p
+    L.lps_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_char_p)]
+    L.lps_last_device_error.restype = ctypes.c_int32
     L.lps_chunk_bins.argtypes = [ctypes.c_int]
     L.lps_chunk_bins.restype = ctypes.c_int32
     dp = ctypes.POINTER(ctypes.c_double)
@@ -113,9 +116,41 @@ def lib():
     return L
 
 
+# Handles whose release was postponed because the calling thread was capturing
+# a graph: the destroy calls synchronise and free device memory, which would
+# invalidate the capture (a garbage-collected Context can be finalised at any
+# point, including inside a capture).
+_DEFERRED = []
+
+
+def _capturing():
+    try:
+        return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
+def _release(destroy, h):
+    _DEFERRED.append((destroy, h))
+    _drain()
+
+
+def _drain():
+    if _capturing():
+        return
+    while _DEFERRED:
+        destroy, h = _DEFERRED.pop(0)
+        getattr(lib(), destroy)(h)
+
+
 def _check(code, where):
     if code != 0:
-        raise LpsError(code, where)
+        detail = None
+        if code == 6:   # LPS_E_DEVICE: name the HIP error behind it
+            name = ctypes.c_char_p()
+            err = lib().lps_last_device_error(ctypes.byref(name))
+            detail = f"HIP error {err} ({name.value.decode() if name.value else '?'})"
+        raise LpsError(code, where, detail)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -161,6 +196,7 @@ class Context:
 
     def __init__(self, f, nk, D, R, route, n_spl, Rfg=None, k_max=64, max_states=1, f_knee=1.0e-3,
                  arm_length=2.5e9, device=None, max_grad_states=None):
+        _drain()
         self.device = torch.device(device if device is not None else "cuda")
         dev = self.device
         self.f = _dev(f, torch.float64, dev)
@@ -193,7 +229,7 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().lps_destroy(self._h)
+            _release("lps_destroy", self._h)
             self._h = None
 
     def __del__(self):
@@ -310,6 +346,7 @@ class Sampler:
 
     def __init__(self, ctx: Context, n_walkers, betas, seed=1, k_in_max=10, step=0.05, precision="mixed",
                  temp_scales=None):
+        _drain()
         self.ctx = ctx
         self.W = int(n_walkers)
         self.betas = np.ascontiguousarray(betas, dtype=np.float64)
@@ -331,7 +368,7 @@ class Sampler:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().lps_sampler_destroy(self._h)
+            _release("lps_sampler_destroy", self._h)
             self._h = None
 
     def __del__(self):

@@ -10,6 +10,20 @@
 
 using lps::Layout;
 
+namespace lps {
+
+namespace {
+thread_local hipError_t g_last_device_error = hipSuccess;
+}
+
+lps_status device_status(hipError_t e) {
+  if (e == hipSuccess) return LPS_OK;
+  g_last_device_error = e;
+  return LPS_E_DEVICE;
+}
+
+}  // namespace lps
+
 namespace {
 
 // Classify the routing table into one of the implemented layouts.
@@ -115,6 +129,12 @@ const char* lps_strerror(lps_status s) {
     case LPS_E_STATE: return "state batch does not provide what the call needs";
   }
   return "unknown status";
+}
+
+int32_t lps_last_device_error(const char** name) {
+  const hipError_t e = lps::g_last_device_error;
+  if (name) *name = hipGetErrorName(e);
+  return (int32_t)e;
 }
 
 int32_t lps_chunk_bins(lps_precision prec) { return prec == LPS_MIXED ? lps::kChunk32 : lps::kChunk64; }
@@ -243,8 +263,7 @@ lps_status lps_psd_build(lps_ctx* ctx, const lps_states* st, int32_t k0, int32_t
   if (k0 < 0 || k1 > ctx->n_bins || k0 > k1) return LPS_E_SHAPE;
   if (st->n_states == 0) return LPS_OK;
   if (!S && k1 > k0) return LPS_E_NULL;
-  return lps::launch_psd(ctx, st, k0, k1, S, Sn, Sh, status, (hipStream_t)stream) == hipSuccess ? LPS_OK
-                                                                                                 : LPS_E_DEVICE;
+  return lps::device_status(lps::launch_psd(ctx, st, k0, k1, S, Sn, Sh, status, (hipStream_t)stream));
 }
 
 lps_status lps_loglike_batch(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL,
@@ -254,8 +273,7 @@ lps_status lps_loglike_batch(lps_ctx* ctx, const lps_states* st, lps_precision p
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
   if (st->n_states == 0) return LPS_OK;
   if (!logL) return LPS_E_NULL;
-  return lps::launch_forward(ctx, st, prec, logL, status, (hipStream_t)stream) == hipSuccess ? LPS_OK
-                                                                                             : LPS_E_DEVICE;
+  return lps::device_status(lps::launch_forward(ctx, st, prec, logL, status, (hipStream_t)stream));
 }
 
 lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL,
@@ -268,10 +286,8 @@ lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st, lps_precis
   if (st->n_states == 0) return LPS_OK;
   if (!logL || !dparams) return LPS_E_NULL;
   if (ctx->n_spl > 0 && (!dknot_x || !dknot_y)) return LPS_E_NULL;
-  return lps::launch_grad(ctx, st, prec, logL, dparams, dknot_x, dknot_y, status, (hipStream_t)stream) ==
-                 hipSuccess
-             ? LPS_OK
-             : LPS_E_DEVICE;
+  return lps::device_status(
+      lps::launch_grad(ctx, st, prec, logL, dparams, dknot_x, dknot_y, status, (hipStream_t)stream));
 }
 
 lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st, double* logL, uint32_t* status,
@@ -280,7 +296,7 @@ lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st, double* lo
   if (r != LPS_OK) return r;
   if (st->n_states == 0) return LPS_OK;
   if (!logL) return LPS_E_NULL;
-  return lps::launch_plain(ctx, st, logL, status, (hipStream_t)stream) == hipSuccess ? LPS_OK : LPS_E_DEVICE;
+  return lps::device_status(lps::launch_plain(ctx, st, logL, status, (hipStream_t)stream));
 }
 
 lps_status lps_set_launch(lps_ctx* ctx, lps_precision prec, int32_t bins_per_lane, int32_t states_per_tile) {

@@ -3,18 +3,23 @@
 // Work item = (state tile, wave chunk of 64*B consecutive bins).  A wave
 // keeps its B bins' table rows in registers for the whole tile and loops over
 // the tile's states, so the shared per-bin data are read from memory once per
-// tile, not once per state.  For each (state, exponent group) the piece
-// holding the chunk is found by a wave-parallel search: lane j compares the
-// chunk's first and last abscissae with breakpoint j+1 and two ballots give
-// the first and last piece indices.  When they agree (the usual case: a chunk
-// spans far less than a knot spacing) the cubic's coefficients are
-// wave-uniform scalar loads; otherwise each lane walks the few breakpoints
-// inside the chunk.  Each bin then evaluates
+// tile, not once per state.  States are taken in sub-tiles of 64/G: lane p
+// locates the piece of (state p / G, group p % G) that holds the chunk's first
+// bin (binary search over the breakpoints), checks whether the next
+// breakpoint falls inside the chunk, and stages the piece's cubic (and, for a
+// crossing chunk, the next piece's) in LDS; ballots mark crossing and invalid
+// pairs.  For the single-precision path the cubic is re-expanded around the
+// start of the table block, so each bin's Horner runs on the stored abscissa.
+// Each bin then evaluates
 //   E_g = exp2(Q_g(x)),  S_c = sum of template rows times E_g  (Eq. (splines)),
 //   l   = sum_c N_k (D~_ck / S~_ck + ln S~_ck)
-// in scaled units, accumulates l in double per lane, and the wave writes one
-// double partial per (state, chunk).  A second kernel adds the partials of a
-// state in a fixed order and the scaling constant C0:
+// in scaled units with one reciprocal and one logarithm for all channels.  A
+// state whose chunk lies inside one piece of every group (the usual case)
+// runs a straight-line body; a crossing state selects the piece per bin.
+// Lane sums are stored transposed in LDS and one lane per state adds the 64
+// of them in a fixed order, in double, giving one partial per (state, chunk).
+// A second kernel adds the partials of a state in a fixed order and the
+// scaling constant C0:
 //   logL = C0 - sum_chunks partial.
 #include <math.h>
 
@@ -59,10 +64,19 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   const int lane = threadIdx.x & (kWave - 1);
   // wave-uniform work-item index: keeps all per-state addressing scalar
   const int wv = uniform(threadIdx.x >> 6);
-  const int item = blockIdx.x * kWavesPerBlock + wv;
-  const int chunk = item % n_chunks;
-  const int t = item / n_chunks;
-  if (t >= n_tiles) return;
+  // Work order: the tiles are taken kTileGroup at a time; within a group the
+  // items run chunk by chunk with the group's tiles innermost, and each XCD
+  // walks one contiguous range of that order.  A chunk's table rows then
+  // reach an XCD's L2 once per tile group instead of once per tile, while the
+  // group's state records (pieces, breakpoints) stay resident in that L2.
+  const int item = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+  const int tg = item / (n_chunks * kTileGroup);
+  const int rem = item - tg * (n_chunks * kTileGroup);
+  const int tl = min(kTileGroup, n_tiles - tg * kTileGroup);   // tiles in this group
+  if (tl <= 0) return;
+  const int chunk = rem / tl;
+  const int t = tg * kTileGroup + (rem - chunk * tl);
+  if (chunk >= n_chunks) return;
   const int s_begin = t * tile;
   const int s_end = min(s_begin + tile, n_states);
   const int kbase = chunk * CH;

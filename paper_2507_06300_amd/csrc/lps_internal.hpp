@@ -145,6 +145,10 @@ namespace lps {
 
 // Launchers implemented in the .hip files.
 hipError_t build_tables(lps_ctx* ctx, hipStream_t s);
+// Maps a HIP result to a status; a failure is remembered (per host thread)
+// for lps_last_device_error.
+lps_status device_status(hipError_t e);
+
 hipError_t launch_coeffs(lps_ctx* ctx, const lps_states* st, hipStream_t s);
 hipError_t launch_forward(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL,
                           uint32_t* status, hipStream_t s);
@@ -182,6 +186,17 @@ __device__ inline float wave_sumf(float v) {
 }
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The chip's eight XCDs (each with its own L2) receive workgroups round-robin
+// by workgroup index.  xcd_block renumbers the grid so that each XCD works
+// through one contiguous range of logical blocks; a bijection on [0, n).
+constexpr int kXcds = 8;
+constexpr int kTileGroup = 4;   // state tiles that share a chunk's table rows in L2
+__device__ inline int xcd_block(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, local = b / kXcds;
+  return x * q + (x < r ? x : r) + local;
+}
 
 // Optional event timing of a main kernel (synchronises; never used under capture).
 inline void timing_begin(lps_ctx* ctx, hipStream_t s) {

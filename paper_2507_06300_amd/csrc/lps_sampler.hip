@@ -599,17 +599,19 @@ lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
   lps_states pro = lps::proposal_states(sm);
   for (int i = 0; i < n_sweeps; ++i) {
     hipLaunchKernelGGL(lps::k_mala_propose, g, b, 0, s, *sm);
-    if (lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s) != hipSuccess)
-      return LPS_E_DEVICE;
+    if (lps_status r = lps::device_status(
+            lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
+      return r;
     hipLaunchKernelGGL(lps::k_mala_accept, g, b, 0, s, *sm);
     hipLaunchKernelGGL(lps::k_rj_propose, g, b, 0, s, *sm);
-    if (lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s) != hipSuccess)
-      return LPS_E_DEVICE;
+    if (lps_status r = lps::device_status(
+            lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
+      return r;
     hipLaunchKernelGGL(lps::k_rj_accept, g, b, 0, s, *sm);
     hipLaunchKernelGGL(lps::k_swap, lps::grid_for(sm->W * (sm->T / 2 + 1), 64), b, 0, s, *sm);
     hipLaunchKernelGGL(lps::k_advance, dim3(1), dim3(64), 0, s, sm->sweep);
   }
-  return hipGetLastError() == hipSuccess ? LPS_OK : LPS_E_DEVICE;
+  return lps::device_status(hipGetLastError());
 }
 
 lps_status lps_sampler_get_state(lps_sampler* sm, double* params, int32_t* knot_off, int32_t* knot_cnt,
@@ -651,7 +653,7 @@ lps_status lps_philox4x32_10(uint64_t seed, uint64_t first_counter, int32_t n, u
   if (n == 0) return LPS_OK;
   hipLaunchKernelGGL(lps::k_philox_fill, lps::grid_for(n, 256), dim3(256), 0, (hipStream_t)stream, seed,
                      first_counter, n, out);
-  return hipGetLastError() == hipSuccess ? LPS_OK : LPS_E_DEVICE;
+  return lps::device_status(hipGetLastError());
 }
 
 }  // extern "C"

@@ -282,3 +282,37 @@ def test_every_launch_shape_matches_oracle(lps, prec, shapes):
     assert ms > 0 and shape[0] in (2, 4, 8)
     got = ctx.loglike_batch(st, prec)[0].cpu().numpy()
     assert np.all(np.abs(got - ref) <= tol)
+
+
+def test_context_dropped_during_capture_is_released_after(lps):
+    """A Context finalised while a graph is being captured (garbage collection
+    can run at any point) must not free device memory inside the capture."""
+    import gc
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=1500, layout="split")
+    sb = W.make_states(name, ds, n_states=8, inbetween=(0, 6))
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    doomed = C.make_context(lps, ds, D, max_states=2)
+    ref = ctx.loglike_batch(st, "mixed")[0].clone()
+    out = torch.empty_like(ref)
+    status = torch.empty(sb.n, dtype=torch.int32, device=ref.device)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.loglike_batch(st, "mixed", out=out, status=status)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.loglike_batch(st, "mixed", out=out, status=status)
+        del doomed
+        gc.collect()
+        assert len(lps._DEFERRED) == 1
+    for _ in range(2):
+        out.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    lps._drain()
+    assert not lps._DEFERRED
