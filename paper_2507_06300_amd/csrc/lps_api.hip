@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "lps_internal.hpp"
@@ -94,7 +95,7 @@ void free_ctx(lps_ctx* c) {
   void* ptrs[] = {c->f,      c->nk,        c->D,       c->R,        c->Rfg,      c->x,       c->sigma,
                   c->tmpl,   c->tab64,     c->tab32,   c->c0,       c->bx,       c->coef64,  c->coef32,
                   c->n_int,  c->scal,      c->status_ws, c->partial, c->gpartial, c->moments, c->plain_part,
-                  c->sticky};
+                  c->sticky, c->wide_list, c->wide_count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -211,6 +212,11 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   ok = ok && dalloc(&c->partial, S * nchunk) == hipSuccess;
   ok = ok && dalloc(&c->plain_part, (size_t)c->plain_blocks) == hipSuccess;
   ok = ok && dalloc(&c->sticky, 1) == hipSuccess;
+  // queue of single-precision chunk partials to re-evaluate in double range
+  // (pairs beyond the capacity keep a non-finite partial: the state is reported invalid)
+  c->wide_cap = (int32_t)std::min<size_t>(S * nchunk, (size_t)1 << 20);
+  ok = ok && dalloc(&c->wide_list, (size_t)c->wide_cap) == hipSuccess;
+  ok = ok && dalloc(&c->wide_count, 1) == hipSuccess;
   if (ok) {
     c->gpartial_bytes = lps::grad_workspace_bytes(c);
     ok = hipMalloc((void**)&c->gpartial, c->gpartial_bytes) == hipSuccess;
@@ -229,6 +235,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   if (L.has_fg)
     cp = cp && hipMemcpy(c->Rfg, d->Rfg, 3 * (size_t)K * sizeof(double), hipMemcpyDeviceToDevice) == hipSuccess;
   cp = cp && hipMemset(c->sticky, 0, sizeof(uint32_t)) == hipSuccess;
+  cp = cp && hipMemset(c->wide_count, 0, sizeof(uint32_t)) == hipSuccess;
   cp = cp && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess;
   cp = cp && lps::build_tables(c, nullptr) == hipSuccess;
   cp = cp && hipDeviceSynchronize() == hipSuccess;

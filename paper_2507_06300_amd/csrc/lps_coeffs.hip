@@ -25,7 +25,9 @@ __global__ __launch_bounds__(256) void k_coeffs(int n_states, int n_spl, int k_m
                                                 const double* __restrict__ ky, double x_first, double x_last,
                                                 double x_knee, double* __restrict__ bx, double* __restrict__ coef64,
                                                 float* __restrict__ coef32, int32_t* __restrict__ n_int,
-                                                StateScalars* __restrict__ scal, uint32_t* __restrict__ status_ws) {
+                                                StateScalars* __restrict__ scal, uint32_t* __restrict__ status_ws,
+                                                uint32_t* __restrict__ wide_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *wide_count = 0u;   // per-call queue of the mixed path
   const int lane = threadIdx.x & (kWave - 1);
   const int s = uniform(blockIdx.x * (blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (s >= n_states) return;
@@ -104,7 +106,8 @@ hipError_t launch_coeffs(lps_ctx* ctx, const lps_states* st, hipStream_t s) {
   hipLaunchKernelGGL(k_coeffs, dim3((n + waves - 1) / waves), dim3(waves * kWave), 0, s, n, ctx->n_spl, ctx->k_max, ctx->lay,
                      ctx->n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->x_first,
                      ctx->x_last,
-                     log10(ctx->f_knee), ctx->bx, ctx->coef64, ctx->coef32, ctx->n_int, ctx->scal, ctx->status_ws);
+                     log10(ctx->f_knee), ctx->bx, ctx->coef64, ctx->coef32, ctx->n_int, ctx->scal, ctx->status_ws,
+                     ctx->wide_count);
   return hipGetLastError();
 }
 

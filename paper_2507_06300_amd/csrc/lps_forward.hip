@@ -30,11 +30,115 @@
 namespace lps {
 namespace {
 
+// 2^q and log2(v) over the double-precision range with single-precision
+// accuracy: the integer part of the exponent is applied exactly (ldexp /
+// frexp) and only the fraction goes through the hardware transcendental.
+__device__ inline double exp2_wide(double q) {
+  const double n = fmin(fmax(floor(q), -2100.0), 2100.0);
+  return ldexp((double)__builtin_amdgcn_exp2f((float)(q - n)), (int)n);
+}
+__device__ inline double log2_wide(double v) {
+  int e = 0;
+  const double m = frexp(v, &e);
+  return (double)e + (double)__builtin_amdgcn_logf((float)m);
+}
+
+// One lane's bins k = kbase + b*64 + lane (b < nb) of state s, evaluated from
+// the FP64 tables and pieces in double range at single-precision accuracy;
+// the piece of each group is located once and then advanced along the lane's
+// increasing abscissae.
+template <int MODE, int NCH, bool FG>
+__device__ double lane_terms_wide(int s, int kbase, int nb, int lane, int K, int k_pad,
+                                  const double* __restrict__ tab64, const double* __restrict__ bx,
+                                  const double* __restrict__ coef64, const int32_t* __restrict__ n_int,
+                                  const StateScalars* __restrict__ scal) {
+  constexpr int G = Groups<MODE>::G;
+  constexpr int NT = FG ? 4 : 3;
+  const StateScalars sc = scal[s];
+  auto row = [&](int r, int k) { return tab64[(size_t)r * k_pad + k]; };
+  int piece[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) piece[g] = -1;
+  double acc = 0.0;
+#pragma unroll 1
+  for (int b = 0; b < nb; ++b) {
+    const int k = kbase + b * kWave + lane;
+    if (k >= K) break;
+    const double x = row(0, k);
+    double S[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) S[c] = FG ? row(tab_k(3, c, NCH), k) * sc.e_fg : 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const size_t base = (size_t)(s * G + g) * kMaxKnots;
+      const int ni = n_int[s * G + g];
+      int i = piece[g];
+      if (i < 0) {
+        i = count_le(bx + base, ni, x);
+      } else {
+        while (i + 1 < ni && bx[base + i + 1] <= x) ++i;
+      }
+      piece[g] = i;
+      const double* cf = coef64 + (base + i) * 4;
+      const double t = x - bx[base + i];
+      const double E = exp2_wide(cf[0] + t * (cf[1] + t * (cf[2] + t * cf[3])));
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        if constexpr (MODE == kSplit) {
+          S[c] += row(tab_k(g, c, NCH), k) * E;
+        } else if constexpr (MODE == kShared) {
+          S[c] += (g == 0 ? sc.w_oms * row(tab_k(0, c, NCH), k) + sc.w_tm * row(tab_k(1, c, NCH), k)
+                          : row(tab_k(2, c, NCH), k)) * E;
+        } else {
+          if (g < 3) {
+            if (c == g) S[c] += (sc.w_oms * row(tab_k(0, c, NCH), k) + sc.w_tm * row(tab_k(1, c, NCH), k)) * E;
+          } else {
+            S[c] += row(tab_k(2, c, NCH), k) * E;
+          }
+        }
+      }
+    }
+    const double nl = row(tab_nl(NT, NCH), k);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const double lw = (NCH == 2 && c == 0) ? 2.0 : 1.0;
+      acc += row(tab_nd(c, NT, NCH), k) / S[c] + lw * nl * log2_wide(S[c]);
+    }
+  }
+  return acc;
+}
+
+// The double-range pass of the mixed path: one wave per queued (state, chunk),
+// a fixed grid striding over the queue (empty in the usual case).  The chunk's
+// partial is replaced by the fixed-order wave sum of its bins' terms.
+template <int MODE, int NCH, bool FG>
+__global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int K, int k_pad,
+                                              const double* __restrict__ tab64, const double* __restrict__ bx,
+                                              const double* __restrict__ coef64, const int32_t* __restrict__ n_int,
+                                              const StateScalars* __restrict__ scal,
+                                              const uint32_t* __restrict__ wide_count,
+                                              const int2* __restrict__ wide_list, int wide_cap,
+                                              double* __restrict__ partial) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+  const int nw = gridDim.x * kWavesPerBlock;
+  const int n = min((int)*wide_count, wide_cap);
+  for (int i = w; i < n; i += nw) {
+    const int2 it = wide_list[i];
+    const int s = uniform(it.x), chunk = uniform(it.y);
+    const double d = wave_sum(lane_terms_wide<MODE, NCH, FG>(s, chunk * chunk_bins, chunk_bins / kWave, lane, K,
+                                                             k_pad, tab64, bx, coef64, n_int, scal));
+    if (lane == 0) partial[(size_t)s * n_chunks + chunk] = d;
+  }
+}
+
 template <typename R, int MODE, int NCH, bool FG, int B>
 __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int n_tiles, int tile, int K,
                                                  int k_pad, int ref_chunk, const R* __restrict__ tab,
                                                  const double* __restrict__ x64, const double* __restrict__ bx,
                                                  const R* __restrict__ coef, const double* __restrict__ coef64,
+                                                 uint32_t* __restrict__ wide_count, int2* __restrict__ wide_list,
+                                                 int wide_cap,
                                                  const int32_t* __restrict__ n_int,
                                                  const StateScalars* __restrict__ scal,
                                                  double* __restrict__ partial) {
@@ -324,6 +428,12 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
 #pragma unroll 8
       for (int i = 0; i < kWave; ++i) sum += (double)red[wv][i * SUB + lane];
       partial[(size_t)(sub + lane) * n_chunks + chunk] = sum;
+      if (kMixed && !isfinite(sum)) {
+        // a channel PSD left the single-precision range (a wildly swinging
+        // spline): queue the (state, chunk) for the double-range pass
+        const unsigned slot = atomicAdd(wide_count, 1u);
+        if (slot < (unsigned)wide_cap) wide_list[slot] = make_int2(sub + lane, chunk);
+      }
     }
     wave_lds_sync();
   }
@@ -358,7 +468,8 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
   const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
 #define LPS_FWD(MODE, NCH, FG)                                                                              \
   hipLaunchKernelGGL((k_forward<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,     \
-                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->coef64, ctx->n_int,    \
+                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->coef64, ctx->wide_count, \
+                     ctx->wide_list, ctx->wide_cap, ctx->n_int,                                               \
                      ctx->scal,                                                                               \
                      ctx->partial)
   const bool fg = L.has_fg != 0;
@@ -373,6 +484,28 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
   else if (L.mode == kPaper && !fg) LPS_FWD(kPaper, 3, false);
   else LPS_FWD(kPaper, 3, true);
 #undef LPS_FWD
+  return hipGetLastError();
+}
+
+hipError_t dispatch_wide(lps_ctx* ctx, int n_chunks, int chunk_bins, hipStream_t s) {
+  const Layout& L = ctx->lay;
+  const dim3 grid(256), block(kWave * kWavesPerBlock);
+#define LPS_WIDE(MODE, NCH, FG)                                                                               \
+  hipLaunchKernelGGL((k_wide<MODE, NCH, FG>), grid, block, 0, s, n_chunks, chunk_bins, ctx->n_bins, ctx->k_pad64, \
+                     ctx->tab64, ctx->bx, ctx->coef64, ctx->n_int, ctx->scal, ctx->wide_count, ctx->wide_list,  \
+                     ctx->wide_cap, ctx->partial)
+  const bool fg = L.has_fg != 0;
+  if (L.mode == kSplit && L.nch == 2 && !fg) LPS_WIDE(kSplit, 2, false);
+  else if (L.mode == kSplit && L.nch == 2 && fg) LPS_WIDE(kSplit, 2, true);
+  else if (L.mode == kSplit && L.nch == 3 && !fg) LPS_WIDE(kSplit, 3, false);
+  else if (L.mode == kSplit && L.nch == 3 && fg) LPS_WIDE(kSplit, 3, true);
+  else if (L.mode == kShared && L.nch == 2 && !fg) LPS_WIDE(kShared, 2, false);
+  else if (L.mode == kShared && L.nch == 2 && fg) LPS_WIDE(kShared, 2, true);
+  else if (L.mode == kShared && L.nch == 3 && !fg) LPS_WIDE(kShared, 3, false);
+  else if (L.mode == kShared && L.nch == 3 && fg) LPS_WIDE(kShared, 3, true);
+  else if (L.mode == kPaper && !fg) LPS_WIDE(kPaper, 3, false);
+  else LPS_WIDE(kPaper, 3, true);
+#undef LPS_WIDE
   return hipGetLastError();
 }
 
@@ -423,6 +556,10 @@ hipError_t launch_forward(lps_ctx* ctx, const lps_states* st, lps_precision prec
   }
   if (e != hipSuccess) return e;
   timing_end(ctx, s);
+  if (mixed) {
+    e = dispatch_wide(ctx, n_chunks, chunk, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_finalize, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kWave * kWavesPerBlock), 0,
                      s, n, n_chunks, ctx->partial, ctx->c0, ctx->status_ws, logL, status);
   return hipGetLastError();

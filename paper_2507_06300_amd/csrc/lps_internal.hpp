@@ -130,6 +130,11 @@ struct lps_ctx {
   double* plain_part;  // [max_states][plain blocks]
   int32_t plain_blocks;
   uint32_t* sticky;    // [1] device error flags
+  // (state, chunk) pairs of a mixed call whose single-precision partial is not
+  // finite, re-evaluated in double range before the final sums
+  int2* wide_list;     // [wide_cap]
+  uint32_t* wide_count;  // [1], cleared by the coefficient kernel of every call
+  int32_t wide_cap;
 
   // launch shapes of the forward kernel: [0] FP64, [1] mixed
   lps::LaunchShape fwd_shape[2];

@@ -13,6 +13,22 @@ from tests import cases as C  # noqa: E402
 NAME = "year_912085bins_4096states"
 
 
+def _largest_spline_excursions(sb, m):
+    """The m states whose splines reach the largest |P| (evaluated by the oracle
+    at nine points per knot interval): where a scaled PSD can leave the
+    single-precision range and the mixed path has to fall back to double range."""
+    from oracle import lps_oracle as O
+    peak = np.zeros(sb.n)
+    for s in range(sb.n):
+        for j in range(sb.n_spl):
+            x, y = sb.knots(s, j)
+            if len(x) < 2:
+                continue
+            xq = np.concatenate([np.linspace(a, b, 9) for a, b in zip(x[:-1], x[1:])])
+            peak[s] = max(peak[s], np.abs(O.spline_eval(x, y, xq)).max())
+    return np.argsort(peak)[-m:].tolist()
+
+
 def test_year_workload_sampled_parity():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -26,9 +42,10 @@ def test_year_workload_sampled_parity():
     lm, sm = ctx.loglike_batch(st, "mixed")
     l64, s64 = ctx.loglike_batch(st, "fp64")
     lm, l64 = lm.cpu().numpy(), l64.cpu().numpy()
-    s64 = s64.cpu().numpy()
+    sm, s64 = sm.cpu().numpy(), s64.cpu().numpy()
     rng = np.random.default_rng(0)
-    sample = sorted(set(rng.choice(sb.n, 8, replace=False).tolist()) | {0, sb.n - 1})
+    extreme = _largest_spline_excursions(sb, 5)
+    sample = sorted(set(rng.choice(sb.n, 8, replace=False).tolist()) | {0, sb.n - 1} | set(extreme))
     ref = C.oracle_loglikes(ds, D, sb, sample)
     ref_st = C.oracle_status(ds, sb, sample)
     tol = C.mixed_tolerance(ds, D, sb, sample)
@@ -36,11 +53,13 @@ def test_year_workload_sampled_parity():
         if not np.isfinite(ref[i]):
             assert not np.isfinite(l64[s])
             continue
-        assert s64[s] == ref_st[i]
+        assert s64[s] == ref_st[i] and sm[s] == ref_st[i]
         assert abs(l64[s] - ref[i]) <= 1e-9 * abs(ref[i]), (s, l64[s], ref[i])
         assert abs(lm[s] - ref[i]) <= tol[i], (s, lm[s], ref[i], tol[i])
-    # properties over every state: FP64 and mixed agree on validity; mixed within
-    # single-precision distance of FP64 for all valid states
-    ok = np.isfinite(l64) & np.isfinite(lm)
+    # properties over every state: FP64 and mixed agree on the status of every
+    # state; mixed within single-precision distance of FP64 for all valid states
+    np.testing.assert_array_equal(sm, s64)
+    ok = np.isfinite(l64)
+    assert np.array_equal(ok, np.isfinite(lm))
     assert ok.sum() >= sb.n - 8
     assert np.all(np.abs(lm[ok] - l64[ok]) <= 1e-6 * np.abs(l64[ok]))

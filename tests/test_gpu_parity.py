@@ -236,25 +236,30 @@ def test_repeatable_and_graph_replay(lps):
 
 
 def test_mixed_extreme_states_keep_fp64_status(lps):
-    """Spline heights far from zero push the per-bin product of channel PSDs out of
-    the single-precision range; the mixed path must still agree with FP64 on which
-    states are valid and on their logL (relative 1e-6)."""
+    """Spline heights far from zero push the per-bin product of channel PSDs, and
+    beyond +-38 dex the channel PSDs themselves, out of the single-precision
+    range; the mixed path must still agree with FP64 on which states are valid
+    and on their logL (relative 1e-6), in every mixed launch shape."""
     name = "grad_25000bins_1024states"
     ds, D = C.dataset_with_data(name, n_bins=2100, layout="split")
-    sb = W.make_states(name, ds, n_states=6, inbetween=(2, 6))
+    shifts = [14.0, -14.0, 20.0, -20.0, 0.0, 11.0, 45.0, -45.0, 60.0, -60.0]
+    sb = W.make_states(name, ds, n_states=len(shifts), inbetween=(2, 6))
     knots = [[(x.copy(), y.copy()) for (x, y) in C.knots_of(sb, s)] for s in range(sb.n)]
-    for s, shift in zip(range(sb.n), [14.0, -14.0, 20.0, -20.0, 0.0, 11.0]):
+    for s, shift in zip(range(sb.n), shifts):
         x, y = knots[s][0]
         knots[s][0] = (x, y + shift)        # OMS spline shifted by `shift` dex
     ext = W.pack_states(sb.params.copy(), knots, 3)
     ctx = C.make_context(lps, ds, D, max_states=ext.n)
     st = C.device_states(ctx, ext)
     l64, s64 = ctx.loglike_batch(st, "fp64")
-    lmx, smx = ctx.loglike_batch(st, "mixed")
-    np.testing.assert_array_equal(s64.cpu().numpy(), smx.cpu().numpy())
-    a, b = l64.cpu().numpy(), lmx.cpu().numpy()
+    a = l64.cpu().numpy()
     ok = np.isfinite(a)
-    assert np.all(np.abs(a[ok] - b[ok]) <= 1e-6 * np.abs(a[ok]))
+    for b, t in [(8, 0), (4, 0), (4, 3)]:
+        ctx.set_launch("mixed", b, t)
+        lmx, smx = ctx.loglike_batch(st, "mixed")
+        np.testing.assert_array_equal(s64.cpu().numpy(), smx.cpu().numpy())
+        bm = lmx.cpu().numpy()
+        assert np.all(np.abs(a[ok] - bm[ok]) <= 1e-6 * np.abs(a[ok])), (b, t)
     ref = C.oracle_loglikes(ds, D, ext)
     assert np.all(np.abs(a[ok] - ref[ok]) <= 1e-9 * np.abs(ref[ok]))
 
@@ -303,12 +308,14 @@ def test_context_dropped_during_capture_is_released_after(lps):
         ctx.loglike_batch(st, "mixed", out=out, status=status)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
+    gc.collect()
+    handle = doomed._h.value
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         ctx.loglike_batch(st, "mixed", out=out, status=status)
         del doomed
         gc.collect()
-        assert len(lps._DEFERRED) == 1
+        assert handle in [h.value for _, h in lps._DEFERRED]
     for _ in range(2):
         out.fill_(0.0)
         g.replay()
