@@ -23,6 +23,8 @@
 //                 template gradients and the Akima backward, lane per knot.
 #include <math.h>
 
+#include <type_traits>
+
 #include "lps_batched.hpp"
 #include "lps_spline.hpp"
 #include "lps_validate.hpp"
@@ -42,10 +44,10 @@ struct RecSize {
   static constexpr int NV = 1 << M;
 };
 
-// 64-lane reduce-scatter of NV = 2^M doubles: on return every lane holds the
+// 64-lane reduce-scatter of NV = 2^M values: on return every lane holds the
 // full sum of value index (lane >> (6 - M)).  Fixed shuffle tree: deterministic.
-template <int M>
-__device__ inline double reduce_scatter(double (&v)[1 << M], int lane) {
+template <int M, typename T>
+__device__ inline T reduce_scatter(T (&v)[1 << M], int lane) {
   constexpr int NV = 1 << M;
 #pragma unroll
   for (int L = 0; L < M; ++L) {
@@ -53,12 +55,12 @@ __device__ inline double reduce_scatter(double (&v)[1 << M], int lane) {
     const bool hi = (lane >> (5 - L)) & 1;
 #pragma unroll
     for (int i = 0; i < half; ++i) {
-      const double keep = hi ? v[half + i] : v[i];
-      const double send = hi ? v[i] : v[half + i];
+      const T keep = hi ? v[half + i] : v[i];
+      const T send = hi ? v[i] : v[half + i];
       v[i] = keep + __shfl_xor(send, 32 >> L, kWave);
     }
   }
-  double r = v[0];
+  T r = v[0];
 #pragma unroll
   for (int off = (32 >> M); off >= 1; off >>= 1) r += __shfl_xor(r, off, kWave);
   return r;
@@ -79,11 +81,29 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
   constexpr int M = RecSize<G>::M;
   constexpr int NV = RecSize<G>::NV;
   constexpr bool kMixed = sizeof(R) == 4;
+  constexpr bool kScalars = FG || MODE != kSplit;
+  using R4 = typename std::conditional<kMixed, float4, double4>::type;
+  // Per wave: the located piece of every (state, group) pair of the sub-tile
+  // and, for a chunk that crosses the next breakpoint, that next piece and the
+  // abscissa where it takes over (all in table units); per-state scalars.
+  __shared__ R4 lc0[kWavesPerBlock][kWave];
+  __shared__ R4 lc1[kWavesPerBlock][kWave];
+  __shared__ R loff0[kWavesPerBlock][kWave];
+  __shared__ R loff1[kWavesPerBlock][kWave];
+  __shared__ R llim[kWavesPerBlock][kWave];
+  __shared__ R lscal[kWavesPerBlock][SUB][4];
   const int lane = threadIdx.x & (kWave - 1);
-  const int item = blockIdx.x * kWavesPerBlock + uniform(threadIdx.x >> 6);
-  const int chunk = item % n_chunks;
-  const int t = item / n_chunks;
-  if (t >= n_tiles) return;
+  const int wv = uniform(threadIdx.x >> 6);
+  // same work order as the forward kernel: tile groups per chunk over
+  // XCD-contiguous block ranges
+  const int item = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+  const int tg = item / (n_chunks * kTileGroup);
+  const int rem = item - tg * (n_chunks * kTileGroup);
+  const int tl = min(kTileGroup, n_tiles - tg * kTileGroup);
+  if (tl <= 0) return;
+  const int chunk = rem / tl;
+  const int t = tg * kTileGroup + (rem - chunk * tl);
+  if (chunk >= n_chunks) return;
   const int s_begin = t * tile;
   const int s_end = min(s_begin + tile, n_states);
   const int kbase = chunk * CH;
@@ -111,86 +131,129 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);
+    // ---- locate: lane p owns the piece of (state sub + p / G, group p % G) ----
     const int ps = lane / G, pg = lane - (lane / G) * G;
     const bool pv = ps < nsub;
     const size_t pbase = (size_t)((sub + ps) * G + pg) * kMaxKnots;
     const int pni = pv ? n_int[(sub + ps) * G + pg] : 0;
     int pi0 = 0, pi1 = 0;
-    R pa = 0, pb = 0, pc = 0, pd = 0, poff = 0;
     if (pni > 0) {
       pi0 = count_le(bx + pbase, pni, xf);
-      pi1 = count_le(bx + pbase, pni, xl);
-      const R* cf = coef + (pbase + pi0) * 4;
-      pa = cf[0];
-      pb = cf[1];
-      pc = cf[2];
-      pd = cf[3];
+      const double b_next = pi0 + 1 < pni ? bx[pbase + pi0 + 1] : (double)INFINITY;
+      pi1 = b_next <= xl ? count_le(bx + pbase, pni, xl) : pi0;
       const double b0 = bx[pbase + pi0];
-      poff = kMixed ? (R)(xo - b0) : (R)(-b0);
+      const R* cf = coef + (pbase + pi0) * 4;
+      R4 r4;
+      r4.x = cf[0];
+      r4.y = cf[1];
+      r4.z = cf[2];
+      r4.w = cf[3];
+      lc0[wv][lane] = r4;
+      loff0[wv][lane] = kMixed ? (R)(xo - b0) : (R)(-b0);
+      if (pi1 > pi0) {
+        const R* cf1 = coef + (pbase + pi0 + 1) * 4;
+        r4.x = cf1[0];
+        r4.y = cf1[1];
+        r4.z = cf1[2];
+        r4.w = cf1[3];
+        lc1[wv][lane] = r4;
+        loff1[wv][lane] = kMixed ? (R)(xo - b_next) : (R)(-b_next);
+        llim[wv][lane] = kMixed ? (R)(b_next - xo) : (R)b_next;
+      }
     }
-    R pw0 = 0, pw1 = 0, pw2 = 0;
-    if (pv && pg == 0) {
-      const StateScalars sc = scal[sub + ps];
-      pw0 = (R)sc.w_oms;
-      pw1 = (R)sc.w_tm;
-      pw2 = (R)sc.e_fg;
+    if constexpr (kScalars) {
+      if (pv && pg == 0) {
+        const StateScalars sc = scal[sub + ps];
+        lscal[wv][ps][0] = (R)sc.w_oms;
+        lscal[wv][ps][1] = (R)sc.w_tm;
+        lscal[wv][ps][2] = (R)sc.e_fg;
+      }
     }
+    const unsigned long long straddle = __ballot(pv && pni > 0 && pi1 > pi0);
+    const unsigned long long multi = __ballot(pv && pni > 0 && pi1 > pi0 + 1);
+    const unsigned long long invalid = __ballot(pv && pg == 0 && pni == 0);
+    unsigned long long cross_state = straddle;
+#pragma unroll
+    for (int g = 1; g < G; ++g) cross_state |= straddle >> g;
+    wave_lds_sync();
 
     for (int q = 0; q < nsub; ++q) {
       const int s = sub + q;
       const size_t ro = (size_t)s * n_chunks + chunk;
-      if (__builtin_amdgcn_readlane(pni, q * G) == 0) {   // invalid state
+      if ((invalid >> (q * G)) & 1ull) {   // invalid state: the finisher reports it
         if (lane < NV) rec[ro * NV + lane] = 0.0;
         if (lane < G) gidx[ro * G + lane] = make_int2(0, 0);
         continue;
       }
-      const R w_oms = readlane_r(pw0, q * G), w_tm = readlane_r(pw1, q * G), e_fg = readlane_r(pw2, q * G);
+      R w_oms = 0, w_tm = 0, e_fg = 0;
+      if constexpr (kScalars) {
+        w_oms = lscal[wv][q][0];
+        w_tm = lscal[wv][q][1];
+        e_fg = lscal[wv][q][2];
+      }
+      const bool crossing = (cross_state >> (q * G)) & 1ull;
 
       // group factors E and piece abscissae T (t = x - x_piece) per bin
       R E[G][B], T[G][B];
-      int gi0[G], gi1[G];
+      if (!crossing) {
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int pl = q * G + g;
-        const int i0 = __builtin_amdgcn_readlane(pi0, pl);
-        const int i1 = __builtin_amdgcn_readlane(pi1, pl);
-        gi0[g] = i0;
-        gi1[g] = i1;
-        if (i0 == i1) {
-          const R a = readlane_r(pa, pl), bb = readlane_r(pb, pl), cc = readlane_r(pc, pl),
-                  dd = readlane_r(pd, pl), off = readlane_r(poff, pl);
+        for (int g = 0; g < G; ++g) {
+          const R4 c0 = lc0[wv][q * G + g];
+          const R o0 = loff0[wv][q * G + g];
 #pragma unroll
           for (int b = 0; b < B; ++b) {
-            T[g][b] = xr[b] + off;
-            E[g][b] = Math<R>::exp2_(a + T[g][b] * (bb + T[g][b] * (cc + T[g][b] * dd)));
+            T[g][b] = xr[b] + o0;
+            E[g][b] = Math<R>::exp2_(c0.x + T[g][b] * (c0.y + T[g][b] * (c0.z + T[g][b] * c0.w)));
           }
-        } else {
-          const size_t base = (size_t)(s * G + g) * kMaxKnots;
-          R Q[B];
-          for (int j = i0; j <= i1; ++j) {
-            const R* cf = coef + (base + j) * 4;
-            const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
-            const double bj = bx[base + j];
-            const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
-            const R lim = kMixed ? (R)(bj - xo) : (R)bj;
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int pl = q * G + g;
+          if (!((multi >> pl) & 1ull)) {   // at most one breakpoint: both staged pieces from LDS
+            const R4 c0 = lc0[wv][pl];
+            const R o0 = loff0[wv][pl];
+            const bool str = (straddle >> pl) & 1ull;
+            const R4 c1 = str ? lc1[wv][pl] : c0;
+            const R o1 = str ? loff1[wv][pl] : o0;
+            const R lim = str ? llim[wv][pl] : (R)INFINITY;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-              const R tt = xr[b] + off;
-              const R qv = a + tt * (bb + tt * (cc + tt * dd));
-              const bool sel = (j == i0) || (xr[b] >= lim);
-              Q[b] = sel ? qv : Q[b];
-              T[g][b] = sel ? tt : T[g][b];
+              const bool second = xr[b] >= lim;
+              const R4 cc = second ? c1 : c0;
+              T[g][b] = xr[b] + (second ? o1 : o0);
+              E[g][b] = Math<R>::exp2_(cc.x + T[g][b] * (cc.y + T[g][b] * (cc.z + T[g][b] * cc.w)));
             }
-          }
+          } else {         // several breakpoints: each piece from memory, select per bin
+            const int i0 = __builtin_amdgcn_readlane(pi0, pl);
+            const int i1 = __builtin_amdgcn_readlane(pi1, pl);
+            const size_t base = (size_t)(s * G + g) * kMaxKnots;
+            R Q[B];
+            for (int j = i0; j <= i1; ++j) {
+              const R* cf = coef + (base + j) * 4;
+              const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
+              const double bj = bx[base + j];
+              const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
+              const R lim = kMixed ? (R)(bj - xo) : (R)bj;
 #pragma unroll
-          for (int b = 0; b < B; ++b) E[g][b] = Math<R>::exp2_(Q[b]);
+              for (int b = 0; b < B; ++b) {
+                const R tt = xr[b] + off;
+                const R qv = a + tt * (bb + tt * (cc + tt * dd));
+                const bool sel = (j == i0) || (xr[b] >= lim);
+                Q[b] = sel ? qv : Q[b];
+                T[g][b] = sel ? tt : T[g][b];
+              }
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) E[g][b] = Math<R>::exp2_(Q[b]);
+          }
         }
       }
 
-      // channel PSDs, score, per-group sensitivities and first-piece moments
-      double vals[NV];
+      // channel PSDs, score, per-group sensitivities; lane sums in R
+      R vf[NV];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) vals[i] = 0.0;
+      for (int i = 0; i < NV; ++i) vf[i] = 0;
       R gq_keep[G][B];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
@@ -217,21 +280,19 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
         }
         const R Nn = NL[b] * (R)(1.0 / kLn2);
         R h[NCH];
-        R lsum = 0;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;
           const R r = Math<R>::rcp_(S[c]);
           const R q1 = ND[c][b] * r;
-          lsum += q1 + (lw * NL[b]) * Math<R>::log2_(S[c]);
+          vf[0] += q1 + (lw * NL[b]) * Math<R>::log2_(S[c]);
           h[c] = (q1 - lw * Nn) * r;       // dlogL/dS~ (scaled units), A and E summed when merged
         }
-        vals[0] += (double)lsum;
-        R fg_sum = 0;
         if constexpr (FG) {
+          R fg_sum = 0;
 #pragma unroll
           for (int c = 0; c < NCH; ++c) fg_sum += h[c] * Kt[3][c][b];
-          vals[3] += (double)(fg_sum * e_fg);
+          vf[3] += fg_sum * e_fg;
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -256,8 +317,8 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
                 at = h[g] * Kt[1][g][b];
               }
               const R ro_ = w_oms * ao * E[g][b], rt_ = w_tm * at * E[g][b];
-              vals[1] += (double)ro_;
-              vals[2] += (double)rt_;
+              vf[1] += ro_;
+              vf[2] += rt_;
               gq = ro_ + rt_;
             } else {
               R a = 0;
@@ -269,82 +330,78 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
           gq_keep[g][b] = gq;
         }
       }
-      // moments of the first piece: bins whose piece index equals i0
+      // moments of the first piece: bins before the next breakpoint
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const int i0 = gi0[g], i1 = gi1[g];
-        R lim1 = 0;
-        if (i1 > i0) {
-          const double b1 = bx[(size_t)(s * G + g) * kMaxKnots + i0 + 1];
-          lim1 = kMixed ? (R)(b1 - xo) : (R)b1;
-        }
-        R m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        const int pl = q * G + g;
+        const R lim1 = ((straddle >> pl) & 1ull) ? llim[wv][pl] : (R)INFINITY;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-          const bool in0 = (i1 == i0) || (xr[b] < lim1);
-          const R gq = in0 ? gq_keep[g][b] : (R)0;
+          const R gq = xr[b] < lim1 ? gq_keep[g][b] : (R)0;
           const R tt = T[g][b];
           const R u1 = gq * tt, u2 = u1 * tt;
-          m0 += gq;
-          m1 += u1;
-          m2 += u2;
-          m3 += u2 * tt;
+          vf[4 + 4 * g + 0] += gq;
+          vf[4 + 4 * g + 1] += u1;
+          vf[4 + 4 * g + 2] += u2;
+          vf[4 + 4 * g + 3] += u2 * tt;
         }
-        vals[4 + 4 * g + 0] += (double)m0;
-        vals[4 + 4 * g + 1] += (double)m1;
-        vals[4 + 4 * g + 2] += (double)m2;
-        vals[4 + 4 * g + 3] += (double)m3;
       }
-      const double red = reduce_scatter<M>(vals, lane);
-      if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = red;
-      if (lane < G) {
+      // the lane sums (B bins each) are added over the wave in the working
+      // precision; the records themselves are double
+      const R red = reduce_scatter<M>(vf, lane);
+      if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = (double)red;
+      {
         int a0 = 0, a1 = 0;
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int g = 0; g < G; ++g) {
+          const int u0 = __builtin_amdgcn_readlane(pi0, q * G + g);
+          const int u1 = __builtin_amdgcn_readlane(pi1, q * G + g);
           if (lane == g) {
-            a0 = gi0[g];
-            a1 = gi1[g];
+            a0 = u0;
+            a1 = u1;
           }
-        gidx[ro * G + lane] = make_int2(a0, a1);
+        }
+        if (lane < G) gidx[ro * G + lane] = make_int2(a0, a1);
       }
-      // later pieces of chunks that straddle knots (rare): interior pieces are
-      // complete here and go straight to the moment table; the last piece is
-      // stitched with the next chunk by the reducer
+      if (!crossing) continue;
+      // later pieces of the groups that cross a breakpoint in this chunk:
+      // interior pieces are complete here and go straight to the moment table;
+      // the last piece is stitched with the next chunk by the finisher
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const int i0 = gi0[g], i1 = gi1[g];
-        if (i1 == i0) continue;
+        const int pl = q * G + g;
+        if (!((straddle >> pl) & 1ull)) continue;
+        const int i0 = __builtin_amdgcn_readlane(pi0, pl);
+        const int i1 = __builtin_amdgcn_readlane(pi1, pl);
         const size_t base = (size_t)(s * G + g) * kMaxKnots;
         for (int j = i0 + 1; j <= i1; ++j) {
-          const double bj = bx[base + j];
-          const R lo = kMixed ? (R)(bj - xo) : (R)bj;
-          R hi = 0;
-          if (j < i1) {
-            const double bj1 = bx[base + j + 1];
-            hi = kMixed ? (R)(bj1 - xo) : (R)bj1;
-          }
-          double mm[4] = {0.0, 0.0, 0.0, 0.0};
+          const R lo = j == i0 + 1 ? llim[wv][pl] : (kMixed ? (R)(bx[base + j] - xo) : (R)bx[base + j]);
+          R hi = (R)INFINITY;
+          if (j < i1) hi = kMixed ? (R)(bx[base + j + 1] - xo) : (R)bx[base + j + 1];
+          R mm[4] = {0, 0, 0, 0};
 #pragma unroll
           for (int b = 0; b < B; ++b) {
-            const bool in = (xr[b] >= lo) && (j == i1 || xr[b] < hi);
+            const bool in = (xr[b] >= lo) && (xr[b] < hi);
             const R gq = in ? gq_keep[g][b] : (R)0;
             const R tt = T[g][b];
             const R u1 = gq * tt, u2 = u1 * tt;
-            mm[0] += (double)gq;
-            mm[1] += (double)u1;
-            mm[2] += (double)u2;
-            mm[3] += (double)(u2 * tt);
+            mm[0] += gq;
+            mm[1] += u1;
+            mm[2] += u2;
+            mm[3] += u2 * tt;
           }
+          double md[4];
 #pragma unroll
-          for (int p = 0; p < 4; ++p) mm[p] = wave_sum(mm[p]);
+          for (int p = 0; p < 4; ++p) md[p] = wave_sum((double)mm[p]);
           if (lane == 0) {
             double* dst = (j == i1) ? glast + (ro * G + g) * 4 : moments + ((size_t)(s * G + g) * kMaxKnots + j) * 4;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) dst[p] = mm[p];
+            for (int p = 0; p < 4; ++p) dst[p] = md[p];
           }
         }
       }
     }
+    wave_lds_sync();
   }
 }
 

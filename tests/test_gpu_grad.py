@@ -147,3 +147,29 @@ def test_autograd_function(lps):
     wk = w.cpu().numpy()[owner]
     np.testing.assert_allclose(kx.grad.cpu().numpy(), dkx.cpu().numpy() * wk, rtol=1e-12)
     np.testing.assert_allclose(ky.grad.cpu().numpy(), dky.cpu().numpy() * wk, rtol=1e-12)
+
+
+def test_gradient_full_batch_sampled(lps):
+    """The gradient workload at its full size (25,000 bins x 1,024 states, several
+    states per work item as in the bench launch), sampled states against the oracle:
+    states at different positions inside the state tiles and sub-tiles."""
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name)
+    sb = W.make_states(name, ds)
+    ctx = C.make_context(lps, ds, D, max_states=sb.n)
+    st = C.device_states(ctx, sb)
+    rng = np.random.default_rng(1)
+    idx = sorted({0, 1, 2, 13, 22, 40, sb.n - 1} | set(rng.choice(sb.n, 5, replace=False).tolist()))
+    sub = W.states_subset(sb, idx)
+    ref = _oracle_grads(ds, D, sub)
+    for prec, rel in (("fp64", 1e-8), ("mixed", 2e-4)):
+        logL, dp, dkx, dky, status = ctx.loglike_grad_batch(st, prec)
+        assert np.all(status.cpu().numpy() == 0)
+        dkx, dky = dkx.cpu().numpy(), dky.cpu().numpy()
+        sx, sy = [], []
+        for s in idx:
+            a, b = int(sb.knot_off[s * sb.n_spl]), int(sb.knot_off[(s + 1) * sb.n_spl])
+            sx.append(dkx[a:b])
+            sy.append(dky[a:b])
+        _compare(sub, ref, logL.cpu().numpy()[idx], dp[:, idx], torch.as_tensor(np.concatenate(sx)),
+                 torch.as_tensor(np.concatenate(sy)), rel, f"{prec} full batch")
