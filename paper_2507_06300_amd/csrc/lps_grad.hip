@@ -44,25 +44,26 @@ struct RecSize {
   static constexpr int NV = 1 << M;
 };
 
-// 64-lane reduce-scatter of NV = 2^M values: on return every lane holds the
-// full sum of value index (lane >> (6 - M)).  Fixed shuffle tree: deterministic.
+// 64-lane reduce-scatter of NV = 2^M values through the wave's LDS block
+// buf[NV][64]: lane l writes its values to column l, then the P = 64 / NV lanes
+// of value v = l >> (6 - M) each add NV consecutive entries of row v in order
+// and finish with an xor butterfly over those P lanes.  On return every lane
+// holds the full sum of value index (lane >> (6 - M)); the order of every sum is
+// fixed, so the result is deterministic.
 template <int M, typename T>
-__device__ inline T reduce_scatter(T (&v)[1 << M], int lane) {
+__device__ inline T reduce_scatter(const T (&v)[1 << M], T* __restrict__ buf, int lane) {
   constexpr int NV = 1 << M;
+  constexpr int P = kWave >> M;
 #pragma unroll
-  for (int L = 0; L < M; ++L) {
-    const int half = NV >> (L + 1);
-    const bool hi = (lane >> (5 - L)) & 1;
+  for (int i = 0; i < NV; ++i) buf[i * kWave + lane] = v[i];
+  wave_lds_sync();
+  const T* row = buf + (lane >> (6 - M)) * kWave + (lane & (P - 1)) * NV;
+  T r = 0;
 #pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const T keep = hi ? v[half + i] : v[i];
-      const T send = hi ? v[i] : v[half + i];
-      v[i] = keep + __shfl_xor(send, 32 >> L, kWave);
-    }
-  }
-  T r = v[0];
+  for (int i = 0; i < NV; ++i) r += row[i];
 #pragma unroll
-  for (int off = (32 >> M); off >= 1; off >>= 1) r += __shfl_xor(r, off, kWave);
+  for (int off = 1; off < P; off <<= 1) r += __shfl_xor(r, off, kWave);
+  wave_lds_sync();
   return r;
 }
 
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
   __shared__ R loff1[kWavesPerBlock][kWave];
   __shared__ R llim[kWavesPerBlock][kWave];
   __shared__ R lscal[kWavesPerBlock][SUB][4];
+  __shared__ R lred[kWavesPerBlock][NV * kWave];   // reduce-scatter transpose
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = uniform(threadIdx.x >> 6);
   // same work order as the forward kernel: tile groups per chunk over
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
       }
       // the lane sums (B bins each) are added over the wave in the working
       // precision; the records themselves are double
-      const R red = reduce_scatter<M>(vf, lane);
+      const R red = reduce_scatter<M>(vf, lred[wv], lane);
       if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = (double)red;
       {
         int a0 = 0, a1 = 0;
