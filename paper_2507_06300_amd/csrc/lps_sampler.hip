@@ -147,24 +147,41 @@ __device__ inline double param_scale(int p) {
 }
 constexpr double kScaleY = 1e-3, kScaleX = 1e-3;
 
-// log prior (up to a constant) of a chain state; -inf outside the support
-__device__ double log_prior(const double* p, int P, int C, int c, const int32_t* off, const int32_t* cnt,
+// Every sweep kernel runs one wave per chain (or chain pair) with one lane per
+// knot slot (capacity <= 64), so knot loops become lane-parallel and the
+// accesses of a chain's padded slots are contiguous.
+__device__ inline int wave_chain(int n) {
+  const int c = uniform((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  return c < n ? c : -1;
+}
+
+// standard normal number d of a chain's stream (pairs from Box-Muller blocks)
+__device__ inline double normal_at(const Rng& g, uint32_t d) {
+  double z0, z1;
+  g.normal2(d >> 1, z0, z1);
+  return (d & 1u) ? z1 : z0;
+}
+
+// log prior (up to a constant) of a chain state; -inf outside the support.
+// Identical on every lane of the wave.
+__device__ double log_prior(int lane, const double* p, int P, int C, int c, const int32_t* off, const int32_t* cnt,
                             const double* kx, const double* ky, int NS, double x_lo, double x_hi) {
+  bool out = lane < P && !param_in_prior(lane, p[lane * (size_t)C + c]);
   double lp = 0.0;
-  for (int q = 0; q < P; ++q)
-    if (!param_in_prior(q, p[q * (size_t)C + c])) return -INFINITY;
   for (int j = 0; j < NS; ++j) {
     const int a = off[c * NS + j], n = cnt[c * NS + j];
-    for (int i = 0; i < n; ++i) {
+    const int i = lane;
+    if (i < n) {
       const double y = ky[a + i];
       lp -= 0.5 * (y / kSigmaW) * (y / kSigmaW);
       if (i > 0 && i < n - 1) {
         const double x = kx[a + i];
-        if (!(x > x_lo && x < x_hi) || !(x > kx[a + i - 1])) return -INFINITY;
+        if (!(x > x_lo && x < x_hi) || !(x > kx[a + i - 1])) out = true;
       }
     }
   }
-  return lp;
+  if (__ballot(out)) return -INFINITY;
+  return wave_sum(lp);
 }
 
 struct ChainView {
@@ -175,80 +192,79 @@ struct ChainView {
   double *gp, *gx, *gy;
 };
 
-__device__ inline void copy_chain(const ChainView& s, const ChainView& d, int c, int C, int P, int NS, int KC,
+__device__ inline void copy_chain(int lane, const ChainView& s, const ChainView& d, int c, int C, int P, int NS,
                                   const int32_t* off, bool with_grad) {
-  for (int q = 0; q < P; ++q) {
-    d.p[q * (size_t)C + c] = s.p[q * (size_t)C + c];
-    if (with_grad) d.gp[q * (size_t)C + c] = s.gp[q * (size_t)C + c];
+  if (lane < P) {
+    d.p[lane * (size_t)C + c] = s.p[lane * (size_t)C + c];
+    if (with_grad) d.gp[lane * (size_t)C + c] = s.gp[lane * (size_t)C + c];
   }
   for (int j = 0; j < NS; ++j) {
     const int a = off[c * NS + j];
     const int n = s.cnt[c * NS + j];
-    d.cnt[c * NS + j] = n;
-    for (int i = 0; i < n; ++i) {
-      d.x[a + i] = s.x[a + i];
-      d.y[a + i] = s.y[a + i];
+    if (lane == 0) d.cnt[c * NS + j] = n;
+    if (lane < n) {
+      d.x[a + lane] = s.x[a + lane];
+      d.y[a + lane] = s.y[a + lane];
       if (with_grad) {
-        d.gx[a + i] = s.gx[a + i];
-        d.gy[a + i] = s.gy[a + i];
+        d.gx[a + lane] = s.gx[a + lane];
+        d.gy[a + lane] = s.gy[a + lane];
       }
     }
   }
-  if (with_grad) {
+  if (with_grad && lane == 0) {
     d.l[c] = s.l[c];
     d.st[c] = s.st[c];
   }
 }
 
 // ---- 1. Langevin proposal ----------------------------------------------------
-__global__ void k_mala_propose(lps_sampler sm) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= sm.C) return;
+// Normal number order per chain: the P template parameters, then per spline
+// and knot the height and (interior knots only) the position.
+__global__ __launch_bounds__(256) void k_mala_propose(lps_sampler sm) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = wave_chain(sm.C);
+  if (c < 0) return;
   const int t = c / sm.W;
   const double beta = sm.beta[t];
   const double h = sm.eps * sm.scale[t];
   const Rng g = make_rng(sm.seed, sm.sweep, c, kPMala);
-  uint32_t draw = 0;
-  double z[2];
-  int zi = 2;
-  auto normal = [&]() {
-    if (zi == 2) {
-      g.normal2(draw++, z[0], z[1]);
-      zi = 0;
-    }
-    return z[zi++];
-  };
   const int C = sm.C;
-  for (int q = 0; q < sm.P; ++q) {
+  if (lane < sm.P) {
+    const int q = lane;
     const double s = h * param_scale(q);
     const double grad = beta * sm.cgp[q * (size_t)C + c];
-    sm.pp[q * (size_t)C + c] = sm.cp[q * (size_t)C + c] + 0.5 * s * s * grad + s * normal();
+    sm.pp[q * (size_t)C + c] = sm.cp[q * (size_t)C + c] + 0.5 * s * s * grad + s * normal_at(g, (uint32_t)q);
   }
+  uint32_t base = (uint32_t)sm.P;
   for (int j = 0; j < sm.NS; ++j) {
     const int a = sm.off[c * sm.NS + j], n = sm.ccnt[c * sm.NS + j];
-    sm.pcnt[c * sm.NS + j] = n;
-    for (int i = 0; i < n; ++i) {
+    if (lane == 0) sm.pcnt[c * sm.NS + j] = n;
+    const int i = lane;
+    if (i < n) {
+      const uint32_t dy = base + (i == 0 ? 0u : 2u * i - 1u);
       const double y = sm.cy[a + i];
       const double sy = h * kScaleY;
       const double gy = beta * sm.cgy[a + i] - y / (kSigmaW * kSigmaW);
-      sm.py[a + i] = y + 0.5 * sy * sy * gy + sy * normal();
+      sm.py[a + i] = y + 0.5 * sy * sy * gy + sy * normal_at(g, dy);
       const double x = sm.cx[a + i];
       if (i == 0 || i == n - 1) {
         sm.px[a + i] = x;   // edge abscissae are fixed
       } else {
         const double sx = h * kScaleX;
-        sm.px[a + i] = x + 0.5 * sx * sx * beta * sm.cgx[a + i] + sx * normal();
+        sm.px[a + i] = x + 0.5 * sx * sx * beta * sm.cgx[a + i] + sx * normal_at(g, dy + 1u);
       }
     }
+    base += (uint32_t)(n >= 2 ? 2 * n - 2 : n);
   }
 }
 
 // log q(to | from) of the Langevin proposal (up to a constant), with the
-// gradient of the tempered log target at `from`
-__device__ double log_q(const ChainView& from, const ChainView& to, int c, int C, int P, int NS, const int32_t* off,
-                        double beta, double h) {
+// gradient of the tempered log target at `from`.  Identical on every lane.
+__device__ double log_q(int lane, const ChainView& from, const ChainView& to, int c, int C, int P, int NS,
+                        const int32_t* off, double beta, double h) {
   double acc = 0.0;
-  for (int q = 0; q < P; ++q) {
+  if (lane < P) {
+    const int q = lane;
     const double s = h * param_scale(q);
     const double m = from.p[q * (size_t)C + c] + 0.5 * s * s * beta * from.gp[q * (size_t)C + c];
     const double d = (to.p[q * (size_t)C + c] - m) / s;
@@ -256,7 +272,8 @@ __device__ double log_q(const ChainView& from, const ChainView& to, int c, int C
   }
   for (int j = 0; j < NS; ++j) {
     const int a = off[c * NS + j], n = from.cnt[c * NS + j];
-    for (int i = 0; i < n; ++i) {
+    const int i = lane;
+    if (i < n) {
       const double sy = h * kScaleY;
       const double gy = beta * from.gy[a + i] - from.y[a + i] / (kSigmaW * kSigmaW);
       const double dy = (to.y[a + i] - from.y[a + i] - 0.5 * sy * sy * gy) / sy;
@@ -268,13 +285,14 @@ __device__ double log_q(const ChainView& from, const ChainView& to, int c, int C
       }
     }
   }
-  return acc;
+  return wave_sum(acc);
 }
 
 // ---- 3. Langevin accept --------------------------------------------------------
-__global__ void k_mala_accept(lps_sampler sm) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= sm.C) return;
+__global__ __launch_bounds__(256) void k_mala_accept(lps_sampler sm) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = wave_chain(sm.C);
+  if (c < 0) return;
   const int t = c / sm.W;
   const double beta = sm.beta[t];
   const double h = sm.eps * sm.scale[t];
@@ -282,30 +300,32 @@ __global__ void k_mala_accept(lps_sampler sm) {
   const ChainView pro = {sm.pp, sm.pcnt, sm.px, sm.py, sm.pl, sm.pst, sm.pgp, sm.pgx, sm.pgy};
   bool accept = false;
   if (sm.pst[c] == 0 && isfinite(sm.pl[c])) {
-    const double lp1 = log_prior(sm.pp, sm.P, sm.C, c, sm.off, sm.pcnt, sm.px, sm.py, sm.NS, sm.x_lo, sm.x_hi);
+    const double lp1 = log_prior(lane, sm.pp, sm.P, sm.C, c, sm.off, sm.pcnt, sm.px, sm.py, sm.NS, sm.x_lo, sm.x_hi);
     if (isfinite(lp1)) {
-      const double lp0 = log_prior(sm.cp, sm.P, sm.C, c, sm.off, sm.ccnt, sm.cx, sm.cy, sm.NS, sm.x_lo, sm.x_hi);
+      const double lp0 =
+          log_prior(lane, sm.cp, sm.P, sm.C, c, sm.off, sm.ccnt, sm.cx, sm.cy, sm.NS, sm.x_lo, sm.x_hi);
       const double dl = (sm.pl[c] - sm.cl[c]) * beta;
-      const double la = dl + (lp1 - lp0) + log_q(pro, cur, c, sm.C, sm.P, sm.NS, sm.off, beta, h) -
-                        log_q(cur, pro, c, sm.C, sm.P, sm.NS, sm.off, beta, h);
+      const double la = dl + (lp1 - lp0) + log_q(lane, pro, cur, c, sm.C, sm.P, sm.NS, sm.off, beta, h) -
+                        log_q(lane, cur, pro, c, sm.C, sm.P, sm.NS, sm.off, beta, h);
       const double u = make_rng(sm.seed, sm.sweep, c, kPMalaAcc).uniform(0);
       accept = log(u) < la;
     }
   }
-  atomicAdd(&sm.counters[(0 * sm.T + t) * 2 + 0], 1u);
-  if (accept) {
-    atomicAdd(&sm.counters[(0 * sm.T + t) * 2 + 1], 1u);
-    copy_chain(pro, cur, c, sm.C, sm.P, sm.NS, sm.KC, sm.off, true);
+  if (lane == 0) {
+    atomicAdd(&sm.counters[(0 * sm.T + t) * 2 + 0], 1u);
+    if (accept) atomicAdd(&sm.counters[(0 * sm.T + t) * 2 + 1], 1u);
   }
+  if (accept) copy_chain(lane, pro, cur, c, sm.C, sm.P, sm.NS, sm.off, true);
 }
 
 // ---- 4. birth / death proposal -------------------------------------------------
-__global__ void k_rj_propose(lps_sampler sm) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= sm.C) return;
+__global__ __launch_bounds__(256) void k_rj_propose(lps_sampler sm) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = wave_chain(sm.C);
+  if (c < 0) return;
   const ChainView cur = {sm.cp, sm.ccnt, sm.cx, sm.cy, sm.cl, sm.cst, sm.cgp, sm.cgx, sm.cgy};
   const ChainView pro = {sm.pp, sm.pcnt, sm.px, sm.py, sm.pl, sm.pst, sm.pgp, sm.pgx, sm.pgy};
-  copy_chain(cur, pro, c, sm.C, sm.P, sm.NS, sm.KC, sm.off, false);
+  copy_chain(lane, cur, pro, c, sm.C, sm.P, sm.NS, sm.off, false);
   const Rng g = make_rng(sm.seed, sm.sweep, c, kPRj);
   const U4 r0 = g.block(0);
   const int j = (int)(r0.x % (uint32_t)sm.NS);
@@ -313,39 +333,41 @@ __global__ void k_rj_propose(lps_sampler sm) {
   const int a = sm.off[c * sm.NS + j];
   const int n = sm.ccnt[c * sm.NS + j];
   const int k_in = n - 2;
+  const int i = lane;
   int ok = 0;
   if (birth && n < sm.KC) {
     const double xs = sm.x_lo + (sm.x_hi - sm.x_lo) * Rng::u01(r0.z, r0.w);
     double z0, z1;
     g.normal2(1, z0, z1);
     const double ys = kSigmaW * z0;
-    int p = n - 1;                       // insert before the first knot above xs (edges stay put)
-    while (p > 1 && sm.px[a + p - 1] > xs) --p;
-    for (int i = n; i > p; --i) {
-      sm.px[a + i] = sm.px[a + i - 1];
-      sm.py[a + i] = sm.py[a + i - 1];
+    // insert after the interior knots at or below xs (edges stay put)
+    const int p = 1 + __popcll(__ballot(i >= 1 && i <= n - 2 && sm.cx[a + i] <= xs));
+    if (i <= n) {
+      const double nx = i < p ? sm.cx[a + i] : (i == p ? xs : sm.cx[a + i - 1]);
+      const double ny = i < p ? sm.cy[a + i] : (i == p ? ys : sm.cy[a + i - 1]);
+      sm.px[a + i] = nx;
+      sm.py[a + i] = ny;
     }
-    sm.px[a + p] = xs;
-    sm.py[a + p] = ys;
-    sm.pcnt[c * sm.NS + j] = n + 1;
+    if (lane == 0) sm.pcnt[c * sm.NS + j] = n + 1;
     ok = (xs > sm.x_lo && xs < sm.x_hi) ? 1 : 0;
   } else if (!birth && k_in > 0) {
     const U4 r1 = g.block(2);
     const int d = 1 + (int)(r1.x % (uint32_t)k_in);   // interior knot to remove
-    for (int i = d; i < n - 1; ++i) {
-      sm.px[a + i] = sm.px[a + i + 1];
-      sm.py[a + i] = sm.py[a + i + 1];
+    if (i >= d && i < n - 1) {
+      sm.px[a + i] = sm.cx[a + i + 1];
+      sm.py[a + i] = sm.cy[a + i + 1];
     }
-    sm.pcnt[c * sm.NS + j] = n - 1;
+    if (lane == 0) sm.pcnt[c * sm.NS + j] = n - 1;
     ok = 1;
   }
-  sm.flag[c] = ok ? (birth ? 1 : 2) : 0;
+  if (lane == 0) sm.flag[c] = ok ? (birth ? 1 : 2) : 0;
 }
 
 // ---- 6. birth / death accept ---------------------------------------------------
-__global__ void k_rj_accept(lps_sampler sm) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= sm.C) return;
+__global__ __launch_bounds__(256) void k_rj_accept(lps_sampler sm) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = wave_chain(sm.C);
+  if (c < 0) return;
   const int t = c / sm.W;
   const int kind = sm.flag[c];           // 1 birth, 2 death, 0 impossible (rejected)
   const int slot = kind == 2 ? 2 : 1;
@@ -355,12 +377,14 @@ __global__ void k_rj_accept(lps_sampler sm) {
     const double u = make_rng(sm.seed, sm.sweep, c, kPRjAcc).uniform(0);
     accept = log(u) < la;
   }
-  atomicAdd(&sm.counters[(slot * sm.T + t) * 2 + 0], 1u);
+  if (lane == 0) {
+    atomicAdd(&sm.counters[(slot * sm.T + t) * 2 + 0], 1u);
+    if (accept) atomicAdd(&sm.counters[(slot * sm.T + t) * 2 + 1], 1u);
+  }
   if (accept) {
-    atomicAdd(&sm.counters[(slot * sm.T + t) * 2 + 1], 1u);
     const ChainView cur = {sm.cp, sm.ccnt, sm.cx, sm.cy, sm.cl, sm.cst, sm.cgp, sm.cgx, sm.cgy};
     const ChainView pro = {sm.pp, sm.pcnt, sm.px, sm.py, sm.pl, sm.pst, sm.pgp, sm.pgx, sm.pgy};
-    copy_chain(pro, cur, c, sm.C, sm.P, sm.NS, sm.KC, sm.off, true);
+    copy_chain(lane, pro, cur, c, sm.C, sm.P, sm.NS, sm.off, true);
   }
 }
 
@@ -371,22 +395,27 @@ __device__ inline void swap_d(double& a, double& b) {
 }
 
 // ---- 7. temperature swaps --------------------------------------------------------
-__global__ void k_swap(lps_sampler sm) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_swap(lps_sampler sm) {
+  const int lane = threadIdx.x & (kWave - 1);
   const int parity = (int)(*sm.sweep & 1ull);
   const int npair = sm.T / 2 + 1;
-  if (id >= sm.W * npair) return;
+  const int id = wave_chain(sm.W * npair);
+  if (id < 0) return;
   const int w = id % sm.W, pair = id / sm.W;
   const int t = 2 * pair + parity;
   if (t + 1 >= sm.T) return;
   const int c1 = t * sm.W + w, c2 = (t + 1) * sm.W + w;
   const double la = (sm.beta[t] - sm.beta[t + 1]) * (sm.cl[c2] - sm.cl[c1]);
   const double u = make_rng(sm.seed, sm.sweep, c1, kPSwap).uniform(0);
-  atomicAdd(&sm.counters[(3 * sm.T + t) * 2 + 0], 1u);
-  if (!(log(u) < la)) return;
-  atomicAdd(&sm.counters[(3 * sm.T + t) * 2 + 1], 1u);
+  const bool accept = log(u) < la;
+  if (lane == 0) {
+    atomicAdd(&sm.counters[(3 * sm.T + t) * 2 + 0], 1u);
+    if (accept) atomicAdd(&sm.counters[(3 * sm.T + t) * 2 + 1], 1u);
+  }
+  if (!accept) return;
   const int C = sm.C;
-  for (int q = 0; q < sm.P; ++q) {
+  if (lane < sm.P) {
+    const int q = lane;
     swap_d(sm.cp[q * (size_t)C + c1], sm.cp[q * (size_t)C + c2]);
     swap_d(sm.cgp[q * (size_t)C + c1], sm.cgp[q * (size_t)C + c2]);
   }
@@ -394,19 +423,24 @@ __global__ void k_swap(lps_sampler sm) {
     const int a1 = sm.off[c1 * sm.NS + j], a2 = sm.off[c2 * sm.NS + j];
     const int n1 = sm.ccnt[c1 * sm.NS + j], n2 = sm.ccnt[c2 * sm.NS + j];
     const int n = n1 > n2 ? n1 : n2;
-    for (int i = 0; i < n; ++i) {
+    const int i = lane;
+    if (i < n) {
       swap_d(sm.cx[a1 + i], sm.cx[a2 + i]);
       swap_d(sm.cy[a1 + i], sm.cy[a2 + i]);
       swap_d(sm.cgx[a1 + i], sm.cgx[a2 + i]);
       swap_d(sm.cgy[a1 + i], sm.cgy[a2 + i]);
     }
-    sm.ccnt[c1 * sm.NS + j] = n2;
-    sm.ccnt[c2 * sm.NS + j] = n1;
+    if (lane == 0) {
+      sm.ccnt[c1 * sm.NS + j] = n2;
+      sm.ccnt[c2 * sm.NS + j] = n1;
+    }
   }
-  swap_d(sm.cl[c1], sm.cl[c2]);
-  const uint32_t s1 = sm.cst[c1];
-  sm.cst[c1] = sm.cst[c2];
-  sm.cst[c2] = s1;
+  if (lane == 0) {
+    swap_d(sm.cl[c1], sm.cl[c2]);
+    const uint32_t s1 = sm.cst[c1];
+    sm.cst[c1] = sm.cst[c2];
+    sm.cst[c2] = s1;
+  }
 }
 
 __global__ void k_advance(unsigned long long* sweep) {
@@ -595,7 +629,7 @@ lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
   if (!sm) return LPS_E_NULL;
   if (n_sweeps < 0) return LPS_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 g = lps::grid_for(sm->C, 64), b(64);
+  const dim3 g = lps::grid_for(sm->C, lps::kWavesPerBlock), b(lps::kWave * lps::kWavesPerBlock);
   lps_states pro = lps::proposal_states(sm);
   for (int i = 0; i < n_sweeps; ++i) {
     hipLaunchKernelGGL(lps::k_mala_propose, g, b, 0, s, *sm);
@@ -608,7 +642,7 @@ lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
             lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
       return r;
     hipLaunchKernelGGL(lps::k_rj_accept, g, b, 0, s, *sm);
-    hipLaunchKernelGGL(lps::k_swap, lps::grid_for(sm->W * (sm->T / 2 + 1), 64), b, 0, s, *sm);
+    hipLaunchKernelGGL(lps::k_swap, lps::grid_for(sm->W * (sm->T / 2 + 1), lps::kWavesPerBlock), b, 0, s, *sm);
     hipLaunchKernelGGL(lps::k_advance, dim3(1), dim3(64), 0, s, sm->sweep);
   }
   return lps::device_status(hipGetLastError());
