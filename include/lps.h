@@ -266,6 +266,30 @@ lps_status lps_sampler_counters(lps_sampler* sm, uint32_t* counters /*[host]*/, 
  * (low word, high word, 0, 0), key = (seed low, seed high)).  Device output. */
 lps_status lps_philox4x32_10(uint64_t seed, uint64_t first_counter, int32_t n, uint32_t* out, void* stream);
 
+/*
+ * Model-selection reductions over stored tempered log-likelihoods.  Samples are
+ * logL[n_rec][n_temps][n_walkers] (device, FP64): records of the sampler's
+ * chain log-likelihoods (lps_sampler_get_state with only logL set copies one
+ * record), chain c = t * n_walkers + w; rung t has n = n_rec * n_walkers draws.
+ * Asynchronous on `stream`, no allocation, deterministic (fixed-order sums).
+ *
+ * Stepping-stone evidence, Eq. (ss) (Sec. "MCMC setup"): betas[n_temps]
+ * (device) strictly increasing, the last normally 1; the ratios run over
+ * consecutive rungs (a lowest rung near 0 stands in for the prior).  out
+ * (device) receives 2 + 2 (n_temps - 1) doubles: log Z, Var(log Z) (delta
+ * method, independent draws), then log r_k and Var(log r_k) for k = 1 .. n_temps - 1.
+ * LPS_E_NULL / LPS_E_SHAPE for missing pointers or n_temps < 2, n_rec < 1, n_walkers < 1.
+ */
+lps_status lps_stepping_stone(const double* betas, int32_t n_temps, const double* logL, int32_t n_rec,
+                              int32_t n_walkers, double* out, void* stream);
+
+/* Deviance information criterion (Sec. "Results"): D = -2 logL over the draws of
+ * rung `rung` (normally the b = 1 rung) and *logL_at_mean (device) = logL at the
+ * posterior-mean parameters.  out (device) receives mean D, p_D = mean D - D(theta_bar),
+ * DIC = mean D + p_D, Var D.  LPS_E_SHAPE for a rung outside [0, n_temps). */
+lps_status lps_dic(const double* logL, int32_t n_rec, int32_t n_temps, int32_t n_walkers, int32_t rung,
+                   const double* logL_at_mean, double* out, void* stream);
+
 /* Synchronise the stream and report the sticky device error flags (0 = none). */
 lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags /*[host]*/);
 

@@ -60,7 +60,8 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error", "lps_strerror",
            "lps_chunk_bins", "lps_last_device_error", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune",
            "lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
-           "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10"]
+           "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10",
+           "lps_stepping_stone", "lps_dic"]
 
 _lib = None
 
@@ -106,8 +107,11 @@ def lib():
     L.lps_sampler_get_state.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]
     L.lps_sampler_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
     L.lps_philox4x32_10.argtypes = [ctypes.c_uint64, ctypes.c_uint64, i32, vp, vp]
+    L.lps_stepping_stone.argtypes = [vp, i32, vp, i32, i32, vp, vp]
+    L.lps_dic.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
-                 "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10"]:
+                 "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
+                 "lps_dic"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -339,6 +343,39 @@ def philox4x32_10(seed: int, first_counter: int, n: int, device="cuda"):
     return (out.to(torch.int64) & 0xFFFFFFFF).view(n, 4)
 
 
+def paper_ladder():
+    """Inverse temperatures of the 20-rung ladder of Sec. "MCMC setup" (increasing):
+    5 log-spaced from 1e-20, 10 from 1e-12, 5 from 1e-5 up to 1."""
+    return np.concatenate([np.logspace(-20, -12, 5, endpoint=False), np.logspace(-12, -5, 10, endpoint=False),
+                           np.logspace(-5, 0, 5)])
+
+
+def stepping_stone(betas, logL: torch.Tensor, stream=None):
+    """Eq. (ss) over logL records [n_rec, T, W] (device FP64): returns
+    (log Z, Var(log Z), log r_k [T-1], Var(log r_k) [T-1]) as host values."""
+    n_rec, T, W = logL.shape
+    lg = logL.contiguous()
+    b = _dev(betas, torch.float64, lg.device)
+    out = torch.empty(2 + 2 * (T - 1), dtype=torch.float64, device=lg.device)
+    _check(lib().lps_stepping_stone(_ptr(b), int(T), _ptr(lg), int(n_rec), int(W), _ptr(out), _stream(stream)),
+           "lps_stepping_stone")
+    o = out.cpu().numpy()
+    return float(o[0]), float(o[1]), o[2:2 + T - 1], o[2 + T - 1:]
+
+
+def dic(logL: torch.Tensor, logL_at_mean, rung=-1, stream=None):
+    """DIC over the draws of one rung of logL records [n_rec, T, W] (device FP64),
+    with logL_at_mean = logL at the posterior-mean parameters: returns
+    (mean D, p_D, DIC, Var D)."""
+    n_rec, T, W = logL.shape
+    lg = logL.contiguous()
+    lm = _dev(np.array([float(logL_at_mean)]), torch.float64, lg.device)
+    out = torch.empty(4, dtype=torch.float64, device=lg.device)
+    _check(lib().lps_dic(_ptr(lg), int(n_rec), int(T), int(W), int(rung % T), _ptr(lm), _ptr(out), _stream(stream)),
+           "lps_dic")
+    return tuple(float(v) for v in out.cpu().numpy())
+
+
 class Sampler:
     """Parallel-tempered reversible-jump sweeps on the device (wraps lps_sampler_*)."""
 
@@ -398,6 +435,13 @@ class Sampler:
                                            _ptr(logL), ctypes.byref(sw), _stream(stream)), "lps_sampler_get_state")
         return {"params": params, "knot_off": off, "knot_cnt": cnt, "knot_x": kx, "knot_y": ky, "logL": logL,
                 "sweep": sw.value}
+
+    def record_logL(self, out_row: torch.Tensor, stream=None):
+        """Copy the chains' current logL [T*W] into out_row (device FP64, e.g. a row
+        of a [n_rec, T, W] record buffer); asynchronous, graph-capturable."""
+        assert out_row.dtype == torch.float64 and out_row.numel() == self.C and out_row.is_contiguous()
+        _check(lib().lps_sampler_get_state(self._h, None, None, None, None, None, _ptr(out_row), None,
+                                           _stream(stream)), "lps_sampler_get_state")
 
     def packed_state(self, stream=None):
         """Current chains as a packed-CSR States batch (for checkpoints and set_state)."""
