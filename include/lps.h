@@ -290,6 +290,36 @@ lps_status lps_stepping_stone(const double* betas, int32_t n_temps, const double
 lps_status lps_dic(const double* logL, int32_t n_rec, int32_t n_temps, int32_t n_walkers, int32_t rung,
                    const double* logL_at_mean, double* out, void* stream);
 
+/*
+ * Data stage: from TDI time series to the inputs of lps_create.
+ *
+ * One-sided periodogram of n_ch time series x[n_ch][n_t] (device, step dt s),
+ * optionally windowed by window[n_t] (device, NULL = none) and, when
+ * xyz_to_aet is non-zero (n_ch = 3), combined first into the noise-orthogonal
+ * channels A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3.
+ * P[n_ch][n_t/2 + 1] (device) receives c_k dt |X_k|^2 / (n_t mean(w^2)) at
+ * f_k = k / (n_t dt), c_k = 1 at k = 0 and k = n_t/2 (n_t even), else 2, with X
+ * the discrete Fourier transform (hipFFT, double).  Allocates temporary device
+ * memory and a transform plan and synchronises `stream`: not for graph capture.
+ */
+lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, double dt, const double* window,
+                                int32_t xyz_to_aet, double* P, void* stream);
+
+/* Averaged periodogram (Sec. "MCMC setup"): n_seg segments of seg_len consecutive
+ * non-overlapping bins starting at bin k0 of P[n_ch][n_f] with frequencies f[n_f]
+ * (device).  D[n_ch][n_seg] = segment means, f_seg[n_seg] = mean bin frequency,
+ * nu[n_seg] = seg_len (the segment counts N_k of lps_create); f_seg and nu may be
+ * NULL.  LPS_E_SHAPE if the segments run past n_f. */
+lps_status lps_data_average(const double* P, int32_t n_ch, int32_t n_f, const double* f, int32_t k0, int32_t seg_len,
+                            int32_t n_seg, double* D, double* f_seg, double* nu, void* stream);
+
+/* Response interpolation (Sec. "Parametrized SGWB model"): grid_R[n_ch][n_g]
+ * tabulated at increasing grid_f[n_g] > 0 Hz, evaluated at f[n] into R[n_ch][n]
+ * (all device): linear in (log f, log R) between nodes whose values are both
+ * positive, linear in (log f, R) otherwise; NaN outside [grid_f[0], grid_f[n_g-1]]. */
+lps_status lps_data_response(const double* grid_f, const double* grid_R, int32_t n_ch, int32_t n_g, const double* f,
+                             int32_t n, double* R, void* stream);
+
 /* Synchronise the stream and report the sticky device error flags (0 = none). */
 lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags /*[host]*/);
 

@@ -61,7 +61,8 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_chunk_bins", "lps_last_device_error", "lps_valu_probe", "lps_set_launch", "lps_get_launch", "lps_autotune",
            "lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
            "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10",
-           "lps_stepping_stone", "lps_dic"]
+           "lps_stepping_stone", "lps_dic",
+           "lps_data_periodogram", "lps_data_average", "lps_data_response"]
 
 _lib = None
 
@@ -109,9 +110,12 @@ def lib():
     L.lps_philox4x32_10.argtypes = [ctypes.c_uint64, ctypes.c_uint64, i32, vp, vp]
     L.lps_stepping_stone.argtypes = [vp, i32, vp, i32, i32, vp, vp]
     L.lps_dic.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
+    L.lps_data_periodogram.argtypes = [vp, i32, i32, ctypes.c_double, vp, i32, vp, vp]
+    L.lps_data_average.argtypes = [vp, i32, i32, vp, i32, i32, i32, vp, vp, vp, vp]
+    L.lps_data_response.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
-                 "lps_dic"]:
+                 "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -343,6 +347,47 @@ def philox4x32_10(seed: int, first_counter: int, n: int, device="cuda"):
     return (out.to(torch.int64) & 0xFFFFFFFF).view(n, 4)
 
 
+def data_periodogram(x: torch.Tensor, dt, window=None, xyz_to_aet=False, stream=None):
+    """One-sided periodogram of time series x [n_ch, n_t] (device FP64): returns
+    (f [n_t//2 + 1], P [n_ch, n_t//2 + 1]) on the device."""
+    xs = _dev(x, torch.float64, x.device)
+    n_ch, n_t = xs.shape
+    w = None if window is None else _dev(window, torch.float64, xs.device)
+    nf = n_t // 2 + 1
+    P = torch.empty((n_ch, nf), dtype=torch.float64, device=xs.device)
+    _check(lib().lps_data_periodogram(_ptr(xs), int(n_ch), int(n_t), float(dt), _ptr(w), 1 if xyz_to_aet else 0,
+                                      _ptr(P), _stream(stream)), "lps_data_periodogram")
+    f = torch.arange(nf, dtype=torch.float64, device=xs.device) / (n_t * float(dt))
+    return f, P
+
+
+def data_average(f: torch.Tensor, P: torch.Tensor, k0, seg_len, n_seg, stream=None):
+    """Averaged periodogram over n_seg segments of seg_len bins from bin k0:
+    returns (f_seg [n_seg], D [n_ch, n_seg], nu [n_seg]) on the device."""
+    Pc = _dev(P, torch.float64, P.device)
+    fc = _dev(f, torch.float64, P.device)
+    n_ch, n_f = Pc.shape
+    D = torch.empty((n_ch, n_seg), dtype=torch.float64, device=Pc.device)
+    fs = torch.empty(n_seg, dtype=torch.float64, device=Pc.device)
+    nu = torch.empty_like(fs)
+    _check(lib().lps_data_average(_ptr(Pc), int(n_ch), int(n_f), _ptr(fc), int(k0), int(seg_len), int(n_seg),
+                                  _ptr(D), _ptr(fs), _ptr(nu), _stream(stream)), "lps_data_average")
+    return fs, D, nu
+
+
+def data_response(grid_f, grid_R, f: torch.Tensor, stream=None):
+    """Response grid_R [n_ch, n_g] at grid_f [n_g] interpolated to f (device):
+    returns R [n_ch, len(f)] on the device."""
+    fc = _dev(f, torch.float64, f.device)
+    gf = _dev(grid_f, torch.float64, fc.device)
+    gR = _dev(np.atleast_2d(grid_R) if not isinstance(grid_R, torch.Tensor) else grid_R, torch.float64, fc.device)
+    n_ch, n_g = gR.shape
+    R = torch.empty((n_ch, fc.numel()), dtype=torch.float64, device=fc.device)
+    _check(lib().lps_data_response(_ptr(gf), _ptr(gR), int(n_ch), int(n_g), _ptr(fc), int(fc.numel()), _ptr(R),
+                                   _stream(stream)), "lps_data_response")
+    return R
+
+
 def paper_ladder():
     """Inverse temperatures of the 20-rung ladder of Sec. "MCMC setup" (increasing):
     5 log-spaced from 1e-20, 10 from 1e-12, 5 from 1e-5 up to 1."""
@@ -354,7 +399,7 @@ def stepping_stone(betas, logL: torch.Tensor, stream=None):
     """Eq. (ss) over logL records [n_rec, T, W] (device FP64): returns
     (log Z, Var(log Z), log r_k [T-1], Var(log r_k) [T-1]) as host values."""
     n_rec, T, W = logL.shape
-    lg = logL.contiguous()
+    lg = _dev(logL, torch.float64, logL.device)
     b = _dev(betas, torch.float64, lg.device)
     out = torch.empty(2 + 2 * (T - 1), dtype=torch.float64, device=lg.device)
     _check(lib().lps_stepping_stone(_ptr(b), int(T), _ptr(lg), int(n_rec), int(W), _ptr(out), _stream(stream)),
@@ -368,7 +413,7 @@ def dic(logL: torch.Tensor, logL_at_mean, rung=-1, stream=None):
     with logL_at_mean = logL at the posterior-mean parameters: returns
     (mean D, p_D, DIC, Var D)."""
     n_rec, T, W = logL.shape
-    lg = logL.contiguous()
+    lg = _dev(logL, torch.float64, logL.device)
     lm = _dev(np.array([float(logL_at_mean)]), torch.float64, lg.device)
     out = torch.empty(4, dtype=torch.float64, device=lg.device)
     _check(lib().lps_dic(_ptr(lg), int(n_rec), int(T), int(W), int(rung % T), _ptr(lm), _ptr(out), _stream(stream)),

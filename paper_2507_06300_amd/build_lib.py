@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblps.so")
 SOURCES = ["lps_api.hip", "lps_tables.hip", "lps_coeffs.hip", "lps_forward.hip", "lps_psd.hip",
-           "lps_plain.hip", "lps_grad.hip", "lps_probe.hip", "lps_sampler.hip", "lps_evidence.hip"]
+           "lps_plain.hip", "lps_grad.hip", "lps_probe.hip", "lps_sampler.hip", "lps_evidence.hip", "lps_data.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -39,7 +39,8 @@ def build(verbose=True, jobs=8):
             procs = []
     _wait(procs, verbose)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-L/opt/rocm/lib", "-lhipfft",
+                                                                                  "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)

@@ -1,0 +1,187 @@
+// Data stage on the device: from TDI time series to the averaged periodogram
+// and the per-bin response that lps_create takes.
+//
+//   periodogram:  X_k = sum_n w_n x_n exp(-2 pi i k n / N) (hipFFT, double),
+//                 P_k = c_k dt |X_k|^2 / (N mean(w^2)),  c_k = 1 at k = 0 and
+//                 k = N/2 (N even), else 2 (one-sided: E[P_k] is the PSD);
+//                 optionally after the XYZ -> AET combination of the series
+//                 A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3.
+//   averaging:    segments of n consecutive non-overlapping bins (Sec. "MCMC
+//                 setup"): D_i = mean of P over the segment, nu_i = n, f_i = mean
+//                 of the segment's bin frequencies.
+//   response:     a response tabulated on a frequency grid, interpolated to the
+//                 analysis frequencies (Sec. "Parametrized SGWB model"): linear
+//                 in (log f, log R) where both grid values are positive, linear
+//                 in (log f, R) otherwise; NaN outside the grid.
+#include <hipfft/hipfft.h>
+#include <math.h>
+
+#include "lps_internal.hpp"
+
+namespace lps {
+namespace {
+
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+constexpr double kInvSqrt3 = 0.57735026918962576451;
+constexpr double kInvSqrt6 = 0.40824829046386301637;
+
+__global__ void k_prep_series(int n_ch, int n, const double* __restrict__ x, const double* __restrict__ w, int aet,
+                              double* __restrict__ xw) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double wi = w ? w[i] : 1.0;
+  if (aet) {
+    const double X = x[i], Y = x[(size_t)n + i], Z = x[2 * (size_t)n + i];
+    xw[i] = wi * ((Z - X) * kInvSqrt2);
+    xw[(size_t)n + i] = wi * ((X - 2.0 * Y + Z) * kInvSqrt6);
+    xw[2 * (size_t)n + i] = wi * ((X + Y + Z) * kInvSqrt3);
+  } else {
+    for (int c = 0; c < n_ch; ++c) xw[(size_t)c * n + i] = wi * x[(size_t)c * n + i];
+  }
+}
+
+// mean(w^2) in one block, fixed order (1 when there is no window)
+__global__ __launch_bounds__(256) void k_window_power(int n, const double* __restrict__ w, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  if (w)
+    for (int i = threadIdx.x; i < n; i += 256) acc += w[i] * w[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = w ? sh[0] / (double)n : 1.0;
+}
+
+__global__ void k_power(int n_ch, int n, int nf, double dt, const hipfftDoubleComplex* __restrict__ X,
+                        const double* __restrict__ w2, double* __restrict__ P) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_ch * nf) return;
+  const int k = (int)(i % nf);
+  const double c = (k == 0 || (n % 2 == 0 && k == n / 2)) ? 1.0 : 2.0;
+  const hipfftDoubleComplex z = X[i];
+  P[i] = c * dt * (z.x * z.x + z.y * z.y) / ((double)n * w2[0]);
+}
+
+__global__ void k_average(int n_ch, int n_f, int k0, int seg_len, int n_seg, const double* __restrict__ P,
+                          const double* __restrict__ f, double* __restrict__ D, double* __restrict__ f_seg,
+                          double* __restrict__ nu) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)(n_ch + 1) * n_seg) return;
+  const int c = (int)(i / n_seg), s = (int)(i % n_seg);
+  const long a = (long)k0 + (long)s * seg_len;
+  const double* src = c < n_ch ? P + (size_t)c * n_f : f;
+  double acc = 0.0;
+  for (int j = 0; j < seg_len; ++j) acc += src[a + j];
+  acc /= (double)seg_len;
+  if (c < n_ch) {
+    D[(size_t)c * n_seg + s] = acc;
+  } else {
+    if (f_seg) f_seg[s] = acc;
+    if (nu) nu[s] = (double)seg_len;
+  }
+}
+
+__global__ void k_response(int n_ch, int n_g, const double* __restrict__ gf, const double* __restrict__ gR, int n,
+                           const double* __restrict__ f, double* __restrict__ R) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_ch * n) return;
+  const int c = (int)(i / n), q = (int)(i % n);
+  const double fq = f[q];
+  double out = NAN;
+  if (fq >= gf[0] && fq <= gf[n_g - 1]) {
+    int lo = 0, hi = n_g - 1;   // last node <= fq, kept below n_g - 1
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (gf[mid] <= fq) lo = mid;
+      else hi = mid;
+    }
+    const double l0 = log(gf[lo]), l1 = log(gf[lo + 1]);
+    const double t = (log(fq) - l0) / (l1 - l0);
+    const double r0 = gR[(size_t)c * n_g + lo], r1 = gR[(size_t)c * n_g + lo + 1];
+    if (r0 > 0.0 && r1 > 0.0) {
+      const double a = log(r0);
+      out = exp(a + t * (log(r1) - a));
+    } else {
+      out = r0 + t * (r1 - r0);
+    }
+  }
+  R[i] = out;
+}
+
+inline dim3 blocks_for(long n, int tpb) { return dim3((unsigned)((n + tpb - 1) / tpb)); }
+
+}  // namespace
+}  // namespace lps
+
+extern "C" {
+
+lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, double dt, const double* window,
+                                int32_t xyz_to_aet, double* P, void* stream) {
+  if (!x || !P) return LPS_E_NULL;
+  if (n_ch < 1 || n_t < 2 || !(dt > 0.0) || (xyz_to_aet && n_ch != 3)) return LPS_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  const int nf = n_t / 2 + 1;
+  double* xw = nullptr;
+  double* w2 = nullptr;
+  hipfftDoubleComplex* X = nullptr;
+  hipfftHandle plan = 0;
+  bool have_plan = false;
+  hipError_t e = hipMalloc((void**)&xw, (size_t)n_ch * n_t * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&X, (size_t)n_ch * nf * sizeof(hipfftDoubleComplex));
+  if (e == hipSuccess) e = hipMalloc((void**)&w2, sizeof(double));
+  lps_status st = LPS_OK;
+  if (e != hipSuccess) st = LPS_E_NOMEM;
+  if (st == LPS_OK) {
+    int n[1] = {n_t};
+    int inembed[1] = {n_t}, onembed[1] = {nf};
+    if (hipfftPlanMany(&plan, 1, n, inembed, 1, n_t, onembed, 1, nf, HIPFFT_D2Z, n_ch) != HIPFFT_SUCCESS ||
+        hipfftSetStream(plan, s) != HIPFFT_SUCCESS) {
+      st = LPS_E_DEVICE;
+    } else {
+      have_plan = true;
+    }
+  }
+  if (st == LPS_OK) {
+    hipLaunchKernelGGL(lps::k_prep_series, lps::blocks_for(n_t, 256), dim3(256), 0, s, n_ch, n_t, x, window,
+                       xyz_to_aet, xw);
+    hipLaunchKernelGGL(lps::k_window_power, dim3(1), dim3(256), 0, s, n_t, window, w2);
+    if (hipfftExecD2Z(plan, (hipfftDoubleReal*)xw, X) != HIPFFT_SUCCESS) st = LPS_E_DEVICE;
+  }
+  if (st == LPS_OK) {
+    hipLaunchKernelGGL(lps::k_power, lps::blocks_for((long)n_ch * nf, 256), dim3(256), 0, s, n_ch, n_t, nf, dt, X,
+                       w2, P);
+    st = lps::device_status(hipGetLastError());
+  }
+  // the temporaries are released after the stream has consumed them
+  const hipError_t sync = hipStreamSynchronize(s);
+  if (st == LPS_OK && sync != hipSuccess) st = lps::device_status(sync);
+  if (have_plan) (void)hipfftDestroy(plan);
+  if (xw) (void)hipFree(xw);
+  if (X) (void)hipFree(X);
+  if (w2) (void)hipFree(w2);
+  return st;
+}
+
+lps_status lps_data_average(const double* P, int32_t n_ch, int32_t n_f, const double* f, int32_t k0, int32_t seg_len,
+                            int32_t n_seg, double* D, double* f_seg, double* nu, void* stream) {
+  if (!P || !f || !D) return LPS_E_NULL;
+  if (n_ch < 1 || n_f < 1 || k0 < 0 || seg_len < 1 || n_seg < 1 || (long)k0 + (long)seg_len * n_seg > n_f)
+    return LPS_E_SHAPE;
+  hipLaunchKernelGGL(lps::k_average, lps::blocks_for((long)(n_ch + 1) * n_seg, 256), dim3(256), 0,
+                     (hipStream_t)stream, n_ch, n_f, k0, seg_len, n_seg, P, f, D, f_seg, nu);
+  return lps::device_status(hipGetLastError());
+}
+
+lps_status lps_data_response(const double* grid_f, const double* grid_R, int32_t n_ch, int32_t n_g, const double* f,
+                             int32_t n, double* R, void* stream) {
+  if (!grid_f || !grid_R || !f || !R) return LPS_E_NULL;
+  if (n_ch < 1 || n_g < 2 || n < 1) return LPS_E_SHAPE;
+  hipLaunchKernelGGL(lps::k_response, lps::blocks_for((long)n_ch * n, 256), dim3(256), 0, (hipStream_t)stream, n_ch,
+                     n_g, grid_f, grid_R, n, f, R);
+  return lps::device_status(hipGetLastError());
+}
+
+}  // extern "C"

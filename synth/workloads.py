@@ -278,3 +278,19 @@ def pack_states(params: np.ndarray, knots, n_spl: int) -> StateBatch:
     return StateBatch(params=np.ascontiguousarray(params, dtype=np.float64), knot_off=off,
                       knot_x=np.concatenate(xs) if xs else np.zeros(0),
                       knot_y=np.concatenate(ys) if ys else np.zeros(0), n_spl=n_spl)
+
+
+def colored_series(rng: np.random.Generator, psd: np.ndarray, n_t: int, dt: float) -> np.ndarray:
+    """Gaussian time series [n_ch][n_t] whose one-sided PSD is psd[n_ch][n_t//2+1]
+    (given on the grid k / (n_t dt); the k = 0 and, for even n_t, Nyquist entries
+    are ignored): Fourier coefficients with E|X_k|^2 = n_t psd_k / (2 dt) and
+    uniform phases, transformed back."""
+    psd = np.atleast_2d(np.asarray(psd, dtype=np.float64))
+    nf = n_t // 2 + 1
+    assert psd.shape[1] == nf
+    amp = np.sqrt(n_t * psd / (2.0 * dt))
+    X = amp * (rng.standard_normal(psd.shape) + 1j * rng.standard_normal(psd.shape)) / np.sqrt(2.0)
+    X[:, 0] = 0.0
+    if n_t % 2 == 0:
+        X[:, -1] = 0.0
+    return np.fft.irfft(X, n=n_t, axis=1)
