@@ -103,6 +103,7 @@ def parse():
     p.add_argument("--sweeps", type=int, default=100,
                    help="sampler sweeps timed on the sweep workload (0 skips the sampler leg)")
     p.add_argument("--sweep-workload", default="sweep_250000bins_2048chains")
+    p.add_argument("--no-data", action="store_true", help="skip the data-stage leg")
     p.add_argument("--launch", default="",
                    help="fixed launch shapes instead of autotuning, e.g. mixed=8x128,fp64=4x64")
     return p.parse_args()
@@ -319,6 +320,10 @@ def main():
     if args.sweeps > 0:
         result["sampler"] = sampler_bench(torch, lps, W, args, dev)
 
+    # --- data stage ------------------------------------------------------------------
+    if not args.no_data:
+        result["data_stage"] = data_stage_bench(torch, lps, dev)
+
     # --- CPU oracle baseline ------------------------------------------------------
     if not args.no_cpu:
         log("cpu oracle sample ...")
@@ -398,9 +403,47 @@ def sampler_bench(torch, lps, W, args, dev):
     res = {"workload": name, "n_bins": K, "chains": n, "walkers": n_walk, "temperatures": n_temps,
            "sweeps": sweeps, "seconds": sec, "sweeps_per_s": sweeps / sec, "ms_per_sweep": sec / sweeps * 1e3,
            "state_bin_grad_evals_per_s": ev / sec, "acceptance": acc, "graph": f"{per_graph} sweeps per graph"}
+    # stepping-stone evidence over logL records of the timed chains (one record per sweep)
+    n_rec = 64
+    rec = torch.empty((n_rec, n_temps, n_walk), dtype=torch.float64, device=dev)
+    for i in range(n_rec):
+        sm.sweep(1)
+        sm.record_logL(rec[i].view(-1))
+    torch.cuda.synchronize()
+    order = np.argsort(betas)                     # the reduction takes an increasing ladder
+    rec_inc = rec[:, torch.as_tensor(order, device=dev), :].contiguous()
+    e0.record()
+    log_z, var_z, _, _ = lps.stepping_stone(betas[order], rec_inc)
+    e1.record()
+    torch.cuda.synchronize()
+    res["evidence"] = {"records": n_rec, "log_z": log_z, "sd_log_z": float(np.sqrt(var_z)),
+                       "ms": e0.elapsed_time(e1)}
     sm.close()
     ctx.close()
     return res
+
+
+def data_stage_bench(torch, lps, dev):
+    """One year of three TDI series (2^21 samples at 15.05 s) through the device
+    data stage: XYZ -> AET, Hann window, periodogram, band of single bins, response."""
+    n_t, dt = 1 << 21, 15.05
+    x = torch.randn((3, n_t), dtype=torch.float64, device=dev)
+    w = torch.hann_window(n_t, periodic=False, dtype=torch.float64, device=dev)
+    gf = np.logspace(np.log10(5e-6), -1, 1000)
+    from synth.workloads import response_standin
+    gR = response_standin(gf)
+    k_lo, k_hi = int(np.ceil(1e-4 * n_t * dt)), int(np.floor(2.9e-2 * n_t * dt))
+    lps.data_periodogram(x, dt, window=w, xyz_to_aet=True)     # plan and kernels warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, P = lps.data_periodogram(x, dt, window=w, xyz_to_aet=True)
+    fs, D, nu = lps.data_average(f, P, k_lo, 1, k_hi - k_lo + 1)
+    R = lps.data_response(gf, gR, fs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    log(f"data stage: {n_t} samples x 3 -> {fs.numel()} bins in {ms:.2f} ms")
+    return {"samples": n_t, "channels": 3, "bins": int(fs.numel()), "ms": ms,
+            "steps": "xyz->aet, hann window, hipFFT periodogram, band of single bins, response interpolation"}
 
 
 if __name__ == "__main__":
