@@ -234,6 +234,8 @@ typedef struct {
   int32_t k_in_max;           /* maximum in-between knots per spline; k_in_max + 2 <= k_max */
   double step;                /* Langevin step multiplier (> 0) */
   lps_precision precision;    /* precision of the likelihood and gradient evaluations */
+  uint32_t fixed_params;      /* bit p set: template parameter p (LPS_P_*) is held fixed (not moved) */
+  int32_t rj_moves;           /* 0: sweeps make no birth/death moves (fixed knot counts) */
 } lps_sampler_desc;
 
 /* Allocate chain storage for n_walkers * n_temps chains (<= max_grad_states of ctx). */

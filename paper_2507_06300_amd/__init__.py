@@ -48,7 +48,8 @@ class _Desc(ctypes.Structure):
 class _SamplerDesc(ctypes.Structure):
     _fields_ = [("n_walkers", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("betas", ctypes.c_void_p),
                 ("temp_scales", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("k_in_max", ctypes.c_int32),
-                ("step", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("step", ctypes.c_double), ("precision", ctypes.c_int), ("fixed_params", ctypes.c_uint32),
+                ("rj_moves", ctypes.c_int32)]
 
 
 class _States(ctypes.Structure):
@@ -427,7 +428,7 @@ class Sampler:
     KINDS = ("langevin", "birth", "death", "swap")
 
     def __init__(self, ctx: Context, n_walkers, betas, seed=1, k_in_max=10, step=0.05, precision="mixed",
-                 temp_scales=None):
+                 temp_scales=None, fixed_params=(), rj_moves=True):
         _drain()
         self.ctx = ctx
         self.W = int(n_walkers)
@@ -444,6 +445,8 @@ class Sampler:
         d.k_in_max = int(k_in_max)
         d.step = float(step)
         d.precision = _PREC.get(precision, precision)
+        d.fixed_params = sum(1 << int(p) for p in fixed_params)
+        d.rj_moves = 1 if rj_moves else 0
         h = ctypes.c_void_p()
         _check(lib().lps_sampler_create(ctx._h, ctypes.byref(d), ctypes.byref(h)), "lps_sampler_create")
         self._h = h

@@ -82,6 +82,8 @@ struct lps_sampler {
   double* scale;                   // [T] step multiplier per temperature
   unsigned long long* sweep;       // [1] sweep counter
   uint32_t* counters;              // [4 kinds][T][2]: proposed, accepted
+  uint32_t fixed;                  // bit p: template parameter p is not moved
+  int rj;                          // birth/death moves on (1) or off (0)
 };
 
 namespace lps {
@@ -231,9 +233,13 @@ __global__ __launch_bounds__(256) void k_mala_propose(lps_sampler sm) {
   const int C = sm.C;
   if (lane < sm.P) {
     const int q = lane;
-    const double s = h * param_scale(q);
-    const double grad = beta * sm.cgp[q * (size_t)C + c];
-    sm.pp[q * (size_t)C + c] = sm.cp[q * (size_t)C + c] + 0.5 * s * s * grad + s * normal_at(g, (uint32_t)q);
+    if ((sm.fixed >> q) & 1u) {
+      sm.pp[q * (size_t)C + c] = sm.cp[q * (size_t)C + c];
+    } else {
+      const double s = h * param_scale(q);
+      const double grad = beta * sm.cgp[q * (size_t)C + c];
+      sm.pp[q * (size_t)C + c] = sm.cp[q * (size_t)C + c] + 0.5 * s * s * grad + s * normal_at(g, (uint32_t)q);
+    }
   }
   uint32_t base = (uint32_t)sm.P;
   for (int j = 0; j < sm.NS; ++j) {
@@ -261,9 +267,9 @@ __global__ __launch_bounds__(256) void k_mala_propose(lps_sampler sm) {
 // log q(to | from) of the Langevin proposal (up to a constant), with the
 // gradient of the tempered log target at `from`.  Identical on every lane.
 __device__ double log_q(int lane, const ChainView& from, const ChainView& to, int c, int C, int P, int NS,
-                        const int32_t* off, double beta, double h) {
+                        const int32_t* off, double beta, double h, uint32_t fixed) {
   double acc = 0.0;
-  if (lane < P) {
+  if (lane < P && !((fixed >> lane) & 1u)) {
     const int q = lane;
     const double s = h * param_scale(q);
     const double m = from.p[q * (size_t)C + c] + 0.5 * s * s * beta * from.gp[q * (size_t)C + c];
@@ -305,8 +311,8 @@ __global__ __launch_bounds__(256) void k_mala_accept(lps_sampler sm) {
       const double lp0 =
           log_prior(lane, sm.cp, sm.P, sm.C, c, sm.off, sm.ccnt, sm.cx, sm.cy, sm.NS, sm.x_lo, sm.x_hi);
       const double dl = (sm.pl[c] - sm.cl[c]) * beta;
-      const double la = dl + (lp1 - lp0) + log_q(lane, pro, cur, c, sm.C, sm.P, sm.NS, sm.off, beta, h) -
-                        log_q(lane, cur, pro, c, sm.C, sm.P, sm.NS, sm.off, beta, h);
+      const double la = dl + (lp1 - lp0) + log_q(lane, pro, cur, c, sm.C, sm.P, sm.NS, sm.off, beta, h, sm.fixed) -
+                        log_q(lane, cur, pro, c, sm.C, sm.P, sm.NS, sm.off, beta, h, sm.fixed);
       const double u = make_rng(sm.seed, sm.sweep, c, kPMalaAcc).uniform(0);
       accept = log(u) < la;
     }
@@ -335,7 +341,9 @@ __global__ __launch_bounds__(256) void k_rj_propose(lps_sampler sm) {
   const int k_in = n - 2;
   const int i = lane;
   int ok = 0;
-  if (birth && n < sm.KC) {
+  if (n == 0) {
+    // a disabled spline stays disabled: no proposal (counted as rejected)
+  } else if (birth && n < sm.KC) {
     const double xs = sm.x_lo + (sm.x_hi - sm.x_lo) * Rng::u01(r0.z, r0.w);
     double z0, z1;
     g.normal2(1, z0, z1);
@@ -457,7 +465,7 @@ __global__ void k_load(lps_sampler sm, const double* __restrict__ params, const 
     const int a = off[c * sm.NS + j];
     const int n = off[c * sm.NS + j + 1] - a;
     const int d = sm.off[c * sm.NS + j];
-    if (n < 2 || n > sm.KC) {
+    if (n == 1 || n < 0 || n > sm.KC) {   // 0 = disabled spline
       atomicOr(bad, 1);
       sm.ccnt[c * sm.NS + j] = 0;
       continue;
@@ -544,6 +552,8 @@ lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* d, lps_sampl
   sm->seed = d->seed;
   sm->eps = d->step;
   sm->prec = d->precision;
+  sm->fixed = d->fixed_params;
+  sm->rj = d->rj_moves != 0;
   sm->x_lo = ctx->x_first;
   sm->x_hi = ctx->x_last;
   const size_t P = sm->P, NS = sm->NS, KC = sm->KC;
@@ -637,11 +647,13 @@ lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
             lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
       return r;
     hipLaunchKernelGGL(lps::k_mala_accept, g, b, 0, s, *sm);
-    hipLaunchKernelGGL(lps::k_rj_propose, g, b, 0, s, *sm);
-    if (lps_status r = lps::device_status(
-            lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
-      return r;
-    hipLaunchKernelGGL(lps::k_rj_accept, g, b, 0, s, *sm);
+    if (sm->rj) {
+      hipLaunchKernelGGL(lps::k_rj_propose, g, b, 0, s, *sm);
+      if (lps_status r = lps::device_status(
+              lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
+        return r;
+      hipLaunchKernelGGL(lps::k_rj_accept, g, b, 0, s, *sm);
+    }
     hipLaunchKernelGGL(lps::k_swap, lps::grid_for(sm->W * (sm->T / 2 + 1), lps::kWavesPerBlock), b, 0, s, *sm);
     hipLaunchKernelGGL(lps::k_advance, dim3(1), dim3(64), 0, s, sm->sweep);
   }
