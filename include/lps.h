@@ -236,6 +236,8 @@ typedef struct {
   lps_precision precision;    /* precision of the likelihood and gradient evaluations */
   uint32_t fixed_params;      /* bit p set: template parameter p (LPS_P_*) is held fixed (not moved) */
   int32_t rj_moves;           /* 0: sweeps make no birth/death moves (fixed knot counts) */
+  int32_t stretch_moves;      /* non-zero: ensemble stretch moves of the free template parameters
+                                 within each temperature, the walker halves in turn (a = 2) */
 } lps_sampler_desc;
 
 /* Allocate chain storage for n_walkers * n_temps chains (<= max_grad_states of ctx). */
@@ -260,8 +262,9 @@ lps_status lps_sampler_get_state(lps_sampler* sm, double* params, int32_t* knot_
                                  double* knot_x, double* knot_y, double* logL, uint64_t* sweep_index /*[host]*/,
                                  void* stream);
 
-/* Move statistics [host] uint32[4][n_temps][2] = (proposed, accepted) for the
- * kinds Langevin, birth, death, swap (swap counted at the lower temperature).  Synchronises. */
+/* Move statistics [host] uint32[5][n_temps][2] = (proposed, accepted) for the
+ * kinds Langevin, birth, death, swap (counted at the lower temperature) and
+ * stretch.  Synchronises. */
 lps_status lps_sampler_counters(lps_sampler* sm, uint32_t* counters /*[host]*/, void* stream);
 
 /* The sampler's generator: out[4i..4i+3] = Philox4x32-10(counter = (first + i) as

@@ -49,7 +49,7 @@ class _SamplerDesc(ctypes.Structure):
     _fields_ = [("n_walkers", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("betas", ctypes.c_void_p),
                 ("temp_scales", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("k_in_max", ctypes.c_int32),
                 ("step", ctypes.c_double), ("precision", ctypes.c_int), ("fixed_params", ctypes.c_uint32),
-                ("rj_moves", ctypes.c_int32)]
+                ("rj_moves", ctypes.c_int32), ("stretch_moves", ctypes.c_int32)]
 
 
 class _States(ctypes.Structure):
@@ -425,10 +425,10 @@ def dic(logL: torch.Tensor, logL_at_mean, rung=-1, stream=None):
 class Sampler:
     """Parallel-tempered reversible-jump sweeps on the device (wraps lps_sampler_*)."""
 
-    KINDS = ("langevin", "birth", "death", "swap")
+    KINDS = ("langevin", "birth", "death", "swap", "stretch")
 
     def __init__(self, ctx: Context, n_walkers, betas, seed=1, k_in_max=10, step=0.05, precision="mixed",
-                 temp_scales=None, fixed_params=(), rj_moves=True):
+                 temp_scales=None, fixed_params=(), rj_moves=True, stretch_moves=False):
         _drain()
         self.ctx = ctx
         self.W = int(n_walkers)
@@ -447,6 +447,7 @@ class Sampler:
         d.precision = _PREC.get(precision, precision)
         d.fixed_params = sum(1 << int(p) for p in fixed_params)
         d.rj_moves = 1 if rj_moves else 0
+        d.stretch_moves = 1 if stretch_moves else 0
         h = ctypes.c_void_p()
         _check(lib().lps_sampler_create(ctx._h, ctypes.byref(d), ctypes.byref(h)), "lps_sampler_create")
         self._h = h
@@ -504,9 +505,10 @@ class Sampler:
         return st, s["sweep"], s["logL"]
 
     def counters(self, stream=None):
-        buf = (ctypes.c_uint32 * (4 * self.T * 2))()
+        k = len(self.KINDS)
+        buf = (ctypes.c_uint32 * (k * self.T * 2))()
         _check(lib().lps_sampler_counters(self._h, buf, _stream(stream)), "lps_sampler_counters")
-        return np.frombuffer(buf, dtype=np.uint32).reshape(4, self.T, 2).copy()
+        return np.frombuffer(buf, dtype=np.uint32).reshape(k, self.T, 2).copy()
 
 
 class LogLikeFn(torch.autograd.Function):

@@ -21,9 +21,11 @@
 //  6. accept with probability min(1, (L'/L)^beta_t): with births from the
 //     prior, a uniform prior on the number of in-between knots and equal
 //     birth/death probabilities, the prior and proposal densities cancel;
-//  7. swaps between adjacent temperatures of each walker (even pairs on even
+//  7. optionally, ensemble stretch moves of the template parameters within each
+//     temperature, the two walker halves in turn (with their adjoint evaluations);
+//  8. swaps between adjacent temperatures of each walker (even pairs on even
 //     sweeps, odd pairs on odd sweeps): accept min(1, exp((b_t - b_{t+1})(L_{t+1} - L_t)));
-//  8. advance the sweep counter.
+//  9. advance the sweep counter.
 // Random numbers come from the counter-based Philox4x32-10 generator of
 // Salmon, Moraes, Dror and Shaw (SC 2011), keyed by the seed and indexed by
 // (chain, sweep, purpose, draw), so results do not depend on launch shapes
@@ -81,15 +83,20 @@ struct lps_sampler {
   double* beta;                    // [T]
   double* scale;                   // [T] step multiplier per temperature
   unsigned long long* sweep;       // [1] sweep counter
-  uint32_t* counters;              // [4 kinds][T][2]: proposed, accepted
+  uint32_t* counters;              // [kKinds][T][2]: proposed, accepted
   uint32_t fixed;                  // bit p: template parameter p is not moved
   int rj;                          // birth/death moves on (1) or off (0)
+  int stretch;                     // ensemble stretch moves on (1) or off (0)
+  double* zs;                      // [C] stretch factor of the pending stretch proposal
 };
 
 namespace lps {
 namespace {
 
-enum Purpose : uint32_t { kPMala = 1, kPMalaAcc = 2, kPRj = 3, kPRjAcc = 4, kPSwap = 5 };
+enum Purpose : uint32_t { kPMala = 1, kPMalaAcc = 2, kPRj = 3, kPRjAcc = 4, kPSwap = 5, kPStretch = 6,
+                          kPStretchAcc = 7 };
+constexpr int kKinds = 5;            // Langevin, birth, death, swap, stretch
+constexpr double kStretchA = 2.0;    // stretch factors z in [1/a, a], density proportional to 1/sqrt(z)
 
 struct Rng {
   uint32_t k0, k1, chain, slo, shi, purpose;
@@ -451,6 +458,71 @@ __global__ __launch_bounds__(256) void k_swap(lps_sampler sm) {
   }
 }
 
+// ---- 8. ensemble stretch move on the template parameters --------------------------
+// Affine-invariant stretch move (Goodman and Weare 2010) within each
+// temperature: the walkers are split into halves w < h and w >= h (h = W / 2);
+// a chain of the moving half draws a partner j uniformly from the other half
+// at its temperature and z from g(z) ~ 1/sqrt(z) on [1/a, a], and proposes
+// theta' = theta_j + z (theta - theta_j) for its free template parameters
+// (knots unchanged).  Accept: (d - 1) log z + beta (L' - L) + log prior ratio,
+// d = number of free parameters.  Chains of the resting half propose their
+// current state (and are not updated).
+__device__ inline bool in_half(int w, int W, int half) { return (w < W / 2) == (half == 0); }
+
+__global__ __launch_bounds__(256) void k_stretch_propose(lps_sampler sm, int half) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = wave_chain(sm.C);
+  if (c < 0) return;
+  const ChainView cur = {sm.cp, sm.ccnt, sm.cx, sm.cy, sm.cl, sm.cst, sm.cgp, sm.cgx, sm.cgy};
+  const ChainView pro = {sm.pp, sm.pcnt, sm.px, sm.py, sm.pl, sm.pst, sm.pgp, sm.pgx, sm.pgy};
+  copy_chain(lane, cur, pro, c, sm.C, sm.P, sm.NS, sm.off, false);
+  const int t = c / sm.W, w = c - t * sm.W;
+  if (!in_half(w, sm.W, half)) return;
+  const int h = sm.W / 2;
+  const int lo = half == 0 ? h : 0, n_other = half == 0 ? sm.W - h : h;
+  const Rng g = make_rng(sm.seed, sm.sweep, c, kPStretch + 8u * (uint32_t)half);
+  const U4 r = g.block(0);
+  const int j = t * sm.W + lo + (int)(r.x % (uint32_t)n_other);
+  const double u = Rng::u01(r.y, r.z);
+  const double sq = (kStretchA - 1.0) * u + 1.0;
+  const double z = sq * sq / kStretchA;
+  if (lane == 0) sm.zs[c] = z;
+  if (lane < sm.P && !((sm.fixed >> lane) & 1u)) {
+    const size_t q = (size_t)lane * sm.C;
+    sm.pp[q + c] = sm.cp[q + j] + z * (sm.cp[q + c] - sm.cp[q + j]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_stretch_accept(lps_sampler sm, int half) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = wave_chain(sm.C);
+  if (c < 0) return;
+  const int t = c / sm.W, w = c - t * sm.W;
+  if (!in_half(w, sm.W, half)) return;
+  int d = 0;
+  for (int q = 0; q < sm.P; ++q) d += ((sm.fixed >> q) & 1u) ? 0 : 1;
+  bool accept = false;
+  if (sm.pst[c] == 0 && isfinite(sm.pl[c])) {
+    const double lp1 = log_prior(lane, sm.pp, sm.P, sm.C, c, sm.off, sm.pcnt, sm.px, sm.py, sm.NS, sm.x_lo, sm.x_hi);
+    if (isfinite(lp1)) {
+      const double lp0 =
+          log_prior(lane, sm.cp, sm.P, sm.C, c, sm.off, sm.ccnt, sm.cx, sm.cy, sm.NS, sm.x_lo, sm.x_hi);
+      const double la = (d - 1) * log(sm.zs[c]) + sm.beta[t] * (sm.pl[c] - sm.cl[c]) + (lp1 - lp0);
+      const double u = make_rng(sm.seed, sm.sweep, c, kPStretchAcc + 8u * (uint32_t)half).uniform(0);
+      accept = log(u) < la;
+    }
+  }
+  if (lane == 0) {
+    atomicAdd(&sm.counters[(4 * sm.T + t) * 2 + 0], 1u);
+    if (accept) atomicAdd(&sm.counters[(4 * sm.T + t) * 2 + 1], 1u);
+  }
+  if (accept) {
+    const ChainView cur = {sm.cp, sm.ccnt, sm.cx, sm.cy, sm.cl, sm.cst, sm.cgp, sm.cgx, sm.cgy};
+    const ChainView pro = {sm.pp, sm.pcnt, sm.px, sm.py, sm.pl, sm.pst, sm.pgp, sm.pgx, sm.pgy};
+    copy_chain(lane, pro, cur, c, sm.C, sm.P, sm.NS, sm.off, true);
+  }
+}
+
 __global__ void k_advance(unsigned long long* sweep) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *sweep += 1ull;
 }
@@ -554,6 +626,7 @@ lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* d, lps_sampl
   sm->prec = d->precision;
   sm->fixed = d->fixed_params;
   sm->rj = d->rj_moves != 0;
+  sm->stretch = d->stretch_moves != 0;
   sm->x_lo = ctx->x_first;
   sm->x_hi = ctx->x_last;
   const size_t P = sm->P, NS = sm->NS, KC = sm->KC;
@@ -576,7 +649,8 @@ lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* d, lps_sampl
   al((void**)&sm->beta, (size_t)sm->T * 8);
   al((void**)&sm->scale, (size_t)sm->T * 8);
   al((void**)&sm->sweep, 8);
-  al((void**)&sm->counters, (size_t)4 * sm->T * 2 * 4);
+  al((void**)&sm->counters, (size_t)lps::kKinds * sm->T * 2 * 4);
+  al((void**)&sm->zs, (size_t)C * 8);
   if (!ok) {
     lps_sampler_destroy(sm);
     return LPS_E_NOMEM;
@@ -592,8 +666,8 @@ lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* d, lps_sampl
   ok = ok && hipMemcpy(sm->sweep, &zero, 8, hipMemcpyHostToDevice) == hipSuccess;
   hipLaunchKernelGGL(lps::k_slot_offsets, lps::grid_for(C * sm->NS, 256), dim3(256), 0, nullptr, C * sm->NS, sm->KC,
                      sm->off);
-  hipLaunchKernelGGL(lps::k_zero_u32, lps::grid_for(4 * sm->T * 2, 64), dim3(64), 0, nullptr, 4 * sm->T * 2,
-                     sm->counters);
+  hipLaunchKernelGGL(lps::k_zero_u32, lps::grid_for(lps::kKinds * sm->T * 2, 64), dim3(64), 0, nullptr,
+                     lps::kKinds * sm->T * 2, sm->counters);
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     lps_sampler_destroy(sm);
@@ -608,7 +682,7 @@ lps_status lps_sampler_destroy(lps_sampler* sm) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {sm->cp,  sm->pp,  sm->off, sm->ccnt, sm->pcnt, sm->cx,  sm->cy,   sm->px,    sm->py,
                   sm->cl,  sm->pl,  sm->cst, sm->pst,  sm->cgp,  sm->pgp, sm->cgx,  sm->cgy,   sm->pgx,
-                  sm->pgy, sm->flag, sm->beta, sm->scale, sm->sweep, sm->counters};
+                  sm->pgy, sm->flag, sm->beta, sm->scale, sm->sweep, sm->counters, sm->zs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete sm;
@@ -654,6 +728,15 @@ lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
         return r;
       hipLaunchKernelGGL(lps::k_rj_accept, g, b, 0, s, *sm);
     }
+    if (sm->stretch && sm->W >= 2) {
+      for (int half = 0; half < 2; ++half) {
+        hipLaunchKernelGGL(lps::k_stretch_propose, g, b, 0, s, *sm, half);
+        if (lps_status r = lps::device_status(
+                lps::launch_grad(sm->ctx, &pro, sm->prec, sm->pl, sm->pgp, sm->pgx, sm->pgy, sm->pst, s)))
+          return r;
+        hipLaunchKernelGGL(lps::k_stretch_accept, g, b, 0, s, *sm, half);
+      }
+    }
     hipLaunchKernelGGL(lps::k_swap, lps::grid_for(sm->W * (sm->T / 2 + 1), lps::kWavesPerBlock), b, 0, s, *sm);
     hipLaunchKernelGGL(lps::k_advance, dim3(1), dim3(64), 0, s, sm->sweep);
   }
@@ -687,7 +770,8 @@ lps_status lps_sampler_get_state(lps_sampler* sm, double* params, int32_t* knot_
 lps_status lps_sampler_counters(lps_sampler* sm, uint32_t* counters, void* stream) {
   if (!sm || !counters) return LPS_E_NULL;
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(counters, sm->counters, (size_t)4 * sm->T * 2 * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(counters, sm->counters, (size_t)lps::kKinds * sm->T * 2 * 4, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return LPS_E_DEVICE;
   return LPS_OK;

@@ -131,3 +131,31 @@ def test_cold_chains_climb_the_likelihood(lps):
     assert np.all(np.isfinite(l1))
     assert np.median(l1) > np.median(l0)
     assert cnt[0, 0, 1] > 0 and cnt[1:3, :, 1].sum() > 0
+
+
+def test_stretch_moves_sample_the_template_prior(lps):
+    """With beta = 0 and ensemble stretch moves on, the walkers spread from a
+    small box over the whole uniform prior of the background amplitude u and
+    slope alpha (Table I ranges of the sampler: u in [-20, -10], alpha in [-5, 5])."""
+    ds, D = C.dataset_with_data(NAME, n_bins=600, layout="split")
+    Wk = 64
+    sb = SW.make_states(NAME, ds, n_states=Wk, inbetween=(0, 3))
+    ctx = C.make_context(lps, ds, D, max_states=Wk)
+    sm = lps.Sampler(ctx, Wk, [0.0], seed=13, k_in_max=5, step=0.05, precision="fp64", rj_moves=False,
+                     stretch_moves=True)
+    sm.set_state(C.device_states(ctx, sb))
+    sm.sweep(300)
+    us, als = [], []
+    for _ in range(80):
+        sm.sweep(5)
+        p = sm.get_state()["params"].cpu().numpy()
+        us.append(p[2])
+        als.append(p[3])
+    u, a = np.concatenate(us), np.concatenate(als)
+    assert u.min() >= -20 and u.max() <= -10 and a.min() >= -5 and a.max() <= 5
+    hu = np.histogram(u, bins=5, range=(-20, -10))[0] / u.size
+    ha = np.histogram(a, bins=5, range=(-5, 5))[0] / a.size
+    print("u hist", hu, "alpha hist", ha, flush=True)
+    assert np.all(np.abs(hu - 0.2) < 0.06) and np.all(np.abs(ha - 0.2) < 0.06)
+    cnt = sm.counters()
+    assert cnt[4, 0, 0] == 700 * Wk and cnt[4, 0, 1] > 0      # every chain once per sweep
