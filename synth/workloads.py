@@ -294,3 +294,41 @@ def colored_series(rng: np.random.Generator, psd: np.ndarray, n_t: int, dt: floa
     if n_t % 2 == 0:
         X[:, -1] = 0.0
     return np.fft.irfft(X, n=n_t, axis=1)
+
+
+def append_splines(sb: StateBatch, rng: np.random.Generator, n_new: int, inbetween, x_lo: float, x_hi: float,
+                   height_sd: float = 0.5) -> StateBatch:
+    """The same states with n_new more spline slots per state, drawn like the
+    others (edge knots at the band extremes, in-between knots uniform in log10 f,
+    heights normal with standard deviation height_sd)."""
+    lo, hi = inbetween
+    knots = []
+    for s in range(sb.n):
+        row = [sb.knots(s, j) for j in range(sb.n_spl)]
+        for _ in range(n_new):
+            c = int(rng.integers(lo, hi + 1)) + 2
+            x = np.concatenate([[x_lo], np.sort(rng.uniform(x_lo, x_hi, c - 2)), [x_hi]])
+            row.append((x, rng.normal(0.0, height_sd, c)))
+        knots.append(row)
+    return pack_states(sb.params, knots, sb.n_spl + n_new)
+
+
+def complex_wishart_mean(rng: np.random.Generator, C: np.ndarray, nu: np.ndarray) -> np.ndarray:
+    """W / nu with W ~ complex Wishart(nu, C): the average of nu outer products
+    z z^H of independent circular complex Gaussian vectors with E[z z^H] = C.
+
+    C is [K][p][p] real symmetric positive definite, nu [K] positive integers.
+    Drawn by the Bartlett decomposition: W = L A A^H L^T with C = L L^T, A lower
+    triangular, |A_ii|^2 ~ Gamma(nu - i, 1) and A_ij ~ CN(0, 1) below the
+    diagonal.  Returns the complex [K][p][p] matrices W / nu."""
+    C = np.asarray(C, dtype=np.float64)
+    K, p, _ = C.shape
+    nu = np.asarray(nu, dtype=np.float64)
+    L = np.linalg.cholesky(C)
+    A = np.zeros((K, p, p), dtype=np.complex128)
+    for i in range(p):
+        A[:, i, i] = np.sqrt(rng.gamma(nu - i, 1.0))
+        for j in range(i):
+            A[:, i, j] = (rng.standard_normal(K) + 1j * rng.standard_normal(K)) / math.sqrt(2.0)
+    LA = L @ A
+    return (LA @ np.conj(np.transpose(LA, (0, 2, 1)))) / nu[:, None, None]

@@ -153,3 +153,52 @@ def test_mutation_route_transposed(monkeypatch):
 
     monkeypatch.setattr(O, "perturbed_terms", wrong)
     assert _fails(pins.test_gradient_matches_finite_differences, "split")
+
+
+# --- full-covariance oracle (reading X1) ---------------------------------
+import oracle.covariance as CV  # noqa: E402
+import tests.test_oracle_covariance as cpins  # noqa: E402
+
+
+def _cov_pins_fail():
+    bodies = [cpins.test_zero_correlation_is_the_diagonal_likelihood,
+              cpins.test_vine_is_positive_definite_with_the_given_partial_correlation,
+              cpins.test_wishart_term_is_stationary_at_the_model,
+              lambda: [cpins.test_one_correlated_pair_is_a_2x2_block(p) for p in ((0, 1), (0, 2), (1, 2))]]
+    return any(_fails(b) for b in bodies)
+
+
+def test_mutation_cov_pair_order(monkeypatch):
+    monkeypatch.setattr(CV, "PAIRS", ((0, 0), (1, 1), (2, 2), (0, 2), (0, 1), (1, 2)))
+    assert _cov_pins_fail()
+
+
+def test_mutation_cov_vine_sign(monkeypatch):
+    def vine(q0, q1, q2):
+        r01, r02, p12 = np.tanh(q0), np.tanh(q1), np.tanh(q2)
+        return r01, r02, -r01 * r02 + p12 * np.sqrt((1 - r01 * r01) * (1 - r02 * r02))
+    monkeypatch.setattr(CV, "vine_correlations", vine)
+    assert _cov_pins_fail()
+
+
+def test_mutation_cov_signal_off_diagonal(monkeypatch):
+    orig = CV.covariance
+
+    def cov(cds, params, knots):
+        C, sn, sh = orig(cds, params, knots)
+        C = C.copy()
+        C[:, 0, 1] += 0.1 * sh[0]
+        C[:, 1, 0] += 0.1 * sh[0]
+        return C, sn, sh
+    monkeypatch.setattr(CV, "covariance", cov)
+    assert _cov_pins_fail()
+
+
+def test_mutation_cov_data_transposed_half(monkeypatch):
+    def dm(P6):
+        M = np.zeros((P6.shape[1], 3, 3))
+        for i, (a, b) in enumerate(CV.PAIRS):
+            M[:, a, b] = P6[i]
+        return M            # lower triangle left empty
+    monkeypatch.setattr(CV, "data_matrix", dm)
+    assert _cov_pins_fail()
