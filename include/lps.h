@@ -325,6 +325,81 @@ lps_status lps_data_average(const double* P, int32_t n_ch, int32_t n_f, const do
 lps_status lps_data_response(const double* grid_f, const double* grid_R, int32_t n_ch, int32_t n_g, const double* f,
                              int32_t n, double* R, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Full-covariance likelihood (dense 3x3 A/E/T covariance per bin).
+ *
+ * The paper keeps the noise covariance diagonal and names the dense treatment
+ * as its extension: three more flexible terms for the off-diagonal entries,
+ * six flexible functions for the noise in all, combined so that the matrix
+ * stays positive definite (Sec. "Power spectral density breakdown", the
+ * paragraph on independent channel splines; outlook of the conclusions).  It
+ * prints no construction; this library uses the following one.
+ *
+ *   Sn_c, Sh_c  noise (OMS + TM) and signal (SGWB + FG) parts of the diagonal
+ *               model above, per channel, with the same templates, parameters
+ *               and routed splines;
+ *   Q_0..Q_2    three further spline slots (abscissa log10 f, P = 0 when
+ *               disabled or routed nowhere);
+ *   r_AE = tanh Q_0,  r_AT = tanh Q_1,
+ *   r_ET = r_AE r_AT + tanh(Q_2) sqrt((1 - r_AE^2)(1 - r_AT^2))
+ *               (tanh Q_2 is the partial correlation of E and T given A; the
+ *               correlation matrix is positive definite for any real Q);
+ *   C_cc = Sn_c + Sh_c,   C_ab = r_ab sqrt(Sn_a Sn_b)   (a != b);
+ *   logL = - sum_k N_k ( tr(C_k^-1 P_k) + ln det C_k ),
+ * the complex-Wishart log-density of an averaged cross-periodogram with
+ * E[P] = C, up to theta-independent constants.  Zero correlations give the
+ * diagonal likelihood of lps_loglike_batch exactly.  Any orthonormal change
+ * of channel basis applied to both C and P (e.g. A/E/T -> X/Y/Z) leaves
+ * logL unchanged, so this is also the dense Michelson-basis likelihood.
+ * A state is invalid (logL = -inf) under the LPS_ST_* rules of the diagonal
+ * model applied to every slot, or with LPS_ST_PSD when C_k is not positive
+ * definite (or not finite) at some bin.  Everything is FP64.
+ * ------------------------------------------------------------------------ */
+#define LPS_COV_MAX_SPLINES 8
+
+typedef struct lps_cov_ctx lps_cov_ctx;
+
+typedef struct {
+  int32_t n_bins;        /* K >= 1 */
+  const double* f;       /* [K] bin frequencies in Hz, strictly increasing, > 0 */
+  const double* nk;      /* [K] N_k >= 1 */
+  const double* P;       /* [6][K] real part of the averaged cross-periodogram, rows
+                            AA, EE, TT, AE, AT, ET; one-sided units, E[P] = C */
+  const double* R;       /* [3][K] SGWB response per channel (as in lps_dataset_desc) */
+  const double* Rfg;     /* [3][K] foreground shape, or NULL */
+  double f_knee;         /* pivot of the power law in Hz */
+  double arm_length;     /* L in m */
+  int32_t n_spl;         /* spline slots per state, 0..LPS_COV_MAX_SPLINES */
+  int8_t route[4][3];    /* diagonal routing as in lps_dataset_desc, any slot or -1 per
+                            (term, channel); route[LPS_TERM_FG][*] must be -1 */
+  int8_t corr[3];        /* slots of Q_0 (A-E), Q_1 (A-T), Q_2 (E-T given A), or -1 */
+  int32_t k_max;         /* max knots per spline including edges, 2..64 */
+  int32_t max_states;    /* workspace capacity in states (>= 1); about 42 KB per state */
+} lps_cov_desc;
+
+/* Create a full-covariance context on `device`: copies the data into a per-bin
+ * table and allocates workspace for max_states.  LPS_E_ROUTING for a slot out
+ * of range or a perturbed foreground.  Synchronises the device. */
+lps_status lps_cov_create(const lps_cov_desc* desc /*[host]*/, int device, lps_cov_ctx** out /*[host]*/);
+
+/* Free a context (NULL is a no-op).  Synchronises the device and frees memory:
+ * not while any stream of the process is being captured into a graph. */
+lps_status lps_cov_destroy(lps_cov_ctx* ctx);
+
+/* logL[s] for every state of the batch (states as in lps_loglike_batch, with
+ * the context's n_spl slots per state).  status (nullable) receives the
+ * LPS_ST_* bits.  Asynchronous on `stream`, no allocation; one batch at a
+ * time per context (the workspace is shared). */
+lps_status lps_cov_loglike_batch(lps_cov_ctx* ctx, const lps_states* st /*[host]*/, double* logL,
+                                 uint32_t* status, void* stream);
+
+/* The model covariance for bins [k0, k1) of every state: C[s][e][k - k0] with
+ * e = AA, EE, TT, AE, AT, ET.  Structurally invalid states get NaN rows and
+ * their status bits (the positive-definiteness bit is left to
+ * lps_cov_loglike_batch).  Asynchronous on `stream`, no allocation. */
+lps_status lps_cov_build(lps_cov_ctx* ctx, const lps_states* st /*[host]*/, int32_t k0, int32_t k1, double* C,
+                         uint32_t* status, void* stream);
+
 /* Synchronise the stream and report the sticky device error flags (0 = none). */
 lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags /*[host]*/);
 

@@ -45,6 +45,14 @@ class _Desc(ctypes.Structure):
                 ("max_grad_states", ctypes.c_int32)]
 
 
+class _CovDesc(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("f", ctypes.c_void_p), ("nk", ctypes.c_void_p),
+                ("P", ctypes.c_void_p), ("R", ctypes.c_void_p), ("Rfg", ctypes.c_void_p),
+                ("f_knee", ctypes.c_double), ("arm_length", ctypes.c_double), ("n_spl", ctypes.c_int32),
+                ("route", ctypes.c_int8 * 12), ("corr", ctypes.c_int8 * 3), ("k_max", ctypes.c_int32),
+                ("max_states", ctypes.c_int32)]
+
+
 class _SamplerDesc(ctypes.Structure):
     _fields_ = [("n_walkers", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("betas", ctypes.c_void_p),
                 ("temp_scales", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("k_in_max", ctypes.c_int32),
@@ -63,7 +71,8 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
            "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10",
            "lps_stepping_stone", "lps_dic",
-           "lps_data_periodogram", "lps_data_average", "lps_data_response"]
+           "lps_data_periodogram", "lps_data_average", "lps_data_response",
+           "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build"]
 
 _lib = None
 
@@ -114,9 +123,14 @@ def lib():
     L.lps_data_periodogram.argtypes = [vp, i32, i32, ctypes.c_double, vp, i32, vp, vp]
     L.lps_data_average.argtypes = [vp, i32, i32, vp, i32, i32, i32, vp, vp, vp, vp]
     L.lps_data_response.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp]
+    L.lps_cov_create.argtypes = [ctypes.POINTER(_CovDesc), ctypes.c_int, ctypes.POINTER(vp)]
+    L.lps_cov_destroy.argtypes = [vp]
+    L.lps_cov_loglike_batch.argtypes = [vp, ctypes.POINTER(_States), vp, vp, vp]
+    L.lps_cov_build.argtypes = [vp, ctypes.POINTER(_States), i32, i32, vp, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
-                 "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response"]:
+                 "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response",
+                 "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -327,6 +341,81 @@ class Context:
         v = ctypes.c_uint32()
         _check(lib().lps_get_error(self._h, _stream(stream), ctypes.byref(v)), "lps_get_error")
         return v.value
+
+
+class CovContext:
+    """Full-covariance (dense 3x3 A/E/T) likelihood for one dataset
+    (wraps lps_cov_create / lps_cov_destroy).  P holds the six real
+    cross-periodogram rows AA, EE, TT, AE, AT, ET; route is the diagonal
+    routing [4][3] and corr the spline slots of the three correlation terms."""
+
+    def __init__(self, f, nk, P, R, route, corr, n_spl, Rfg=None, k_max=64, max_states=1, f_knee=1.0e-3,
+                 arm_length=2.5e9, device=None):
+        _drain()
+        self.device = torch.device(device if device is not None else "cuda")
+        dev = self.device
+        self.f = _dev(f, torch.float64, dev)
+        self.nk = _dev(nk, torch.float64, dev)
+        self.P = _dev(P, torch.float64, dev)
+        self.R = _dev(R, torch.float64, dev)
+        self.Rfg = None if Rfg is None else _dev(Rfg, torch.float64, dev)
+        self.n_bins = int(self.f.numel())
+        self.n_spl = int(n_spl)
+        self.max_states = int(max_states)
+        d = _CovDesc()
+        d.n_bins = self.n_bins
+        d.f, d.nk, d.P, d.R = (self.f.data_ptr(), self.nk.data_ptr(), self.P.data_ptr(), self.R.data_ptr())
+        d.Rfg = None if self.Rfg is None else self.Rfg.data_ptr()
+        d.f_knee = float(f_knee)
+        d.arm_length = float(arm_length)
+        d.n_spl = self.n_spl
+        flat = [int(v) for row in route for v in row]
+        for i in range(12):
+            d.route[i] = flat[i]
+        for i in range(3):
+            d.corr[i] = int(corr[i])
+        d.k_max = int(k_max)
+        d.max_states = self.max_states
+        h = ctypes.c_void_p()
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        _check(lib().lps_cov_create(ctypes.byref(d), idx, ctypes.byref(h)), "lps_cov_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _release("lps_cov_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def states(self, params, knot_off, knot_x, knot_y) -> States:
+        dev = self.device
+        return States(_dev(params, torch.float64, dev), _dev(knot_off, torch.int32, dev),
+                      _dev(knot_x, torch.float64, dev), _dev(knot_y, torch.float64, dev))
+
+    def loglike_batch(self, st: States, out=None, status=None, stream=None):
+        n = st.n
+        logL = out if out is not None else torch.empty(n, dtype=torch.float64, device=self.device)
+        status = status if status is not None else torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_cov_loglike_batch(self._h, ctypes.byref(c), _ptr(logL), _ptr(status), _stream(stream)),
+               "lps_cov_loglike_batch")
+        return logL, status
+
+    def build(self, st: States, k0=0, k1=None, stream=None):
+        """Model covariance rows C[s][6][k1 - k0] (AA, EE, TT, AE, AT, ET) and status."""
+        k1 = self.n_bins if k1 is None else int(k1)
+        n = st.n
+        C = torch.empty((n, 6, k1 - int(k0)), dtype=torch.float64, device=self.device)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_cov_build(self._h, ctypes.byref(c), int(k0), int(k1), _ptr(C), _ptr(status),
+                                   _stream(stream)), "lps_cov_build")
+        return C, status
 
 
 def valu_probe(device=0):

@@ -20,19 +20,8 @@ __global__ void k_templates(int K, const double* __restrict__ f, double L, const
   if (k >= K) return;
   double fk = f[k];
   x[k] = log10(fk);
-  double xi = 2.0 * kPi * fk * L / kClight;
-  double sx = sin(xi), cx = cos(xi), s2x = sin(2.0 * xi);
-  double pref = sx * sx * s2x * s2x;
-  double r2 = 2.0e-3 / fk;
-  double s_oms = (1.0 + r2 * r2 * r2 * r2) * (2.0 * kPi * fk / kClight) * (2.0 * kPi * fk / kClight);
-  double r4 = 0.4e-3 / fk, r8 = fk / 8.0e-3;
-  double q = 1.0 / (2.0 * kPi * fk * kClight);
-  double s_tm = (1.0 + r4 * r4) * (1.0 + r8 * r8 * r8 * r8) * q * q;
-  double oms_ae = 32.0 * pref * (2.0 + cx) * s_oms;
-  double tm_ae = 32.0 * pref * 4.0 * (1.0 + cx + cx * cx) * s_tm;
-  double oms_t = 64.0 * pref * (1.0 - cx) * s_oms;
-  double tm_t = 64.0 * pref * 2.0 * (1.0 - cx) * (1.0 - cx) * s_tm;
-  double h = 3.0 * kH0PerH * kH0PerH / (4.0 * kPi * kPi * fk * fk * fk);
+  double oms_ae, oms_t, tm_ae, tm_t, h;
+  unit_templates(fk, L, oms_ae, oms_t, tm_ae, tm_t, h);
   double oms[3] = {oms_ae, oms_ae, oms_t};
   double tm[3] = {tm_ae, tm_ae, tm_t};
   for (int c = 0; c < 3; ++c) {

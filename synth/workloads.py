@@ -320,15 +320,28 @@ def complex_wishart_mean(rng: np.random.Generator, C: np.ndarray, nu: np.ndarray
     C is [K][p][p] real symmetric positive definite, nu [K] positive integers.
     Drawn by the Bartlett decomposition: W = L A A^H L^T with C = L L^T, A lower
     triangular, |A_ii|^2 ~ Gamma(nu - i, 1) and A_ij ~ CN(0, 1) below the
-    diagonal.  Returns the complex [K][p][p] matrices W / nu."""
+    diagonal.  Bins with nu < p (a singular Wishart) sum nu outer products of
+    draws L g, g ~ CN(0, I), instead.  Returns the complex [K][p][p] matrices W / nu."""
     C = np.asarray(C, dtype=np.float64)
     K, p, _ = C.shape
     nu = np.asarray(nu, dtype=np.float64)
     L = np.linalg.cholesky(C)
+    few = nu < p
+    nu_b = np.where(few, float(p), nu)
     A = np.zeros((K, p, p), dtype=np.complex128)
     for i in range(p):
-        A[:, i, i] = np.sqrt(rng.gamma(nu - i, 1.0))
+        A[:, i, i] = np.sqrt(rng.gamma(nu_b - i, 1.0))
         for j in range(i):
             A[:, i, j] = (rng.standard_normal(K) + 1j * rng.standard_normal(K)) / math.sqrt(2.0)
     LA = L @ A
-    return (LA @ np.conj(np.transpose(LA, (0, 2, 1)))) / nu[:, None, None]
+    W = LA @ np.conj(np.transpose(LA, (0, 2, 1)))
+    if np.any(few):
+        idx = np.nonzero(few)[0]
+        Wf = np.zeros((idx.size, p, p), dtype=np.complex128)
+        for m in range(1, p):
+            sel = nu[idx] >= m
+            g = (rng.standard_normal((idx.size, p)) + 1j * rng.standard_normal((idx.size, p))) / math.sqrt(2.0)
+            z = np.einsum("kab,kb->ka", L[idx], g)
+            Wf += sel[:, None, None] * (z[:, :, None] * np.conj(z[:, None, :]))
+        W[idx] = Wf
+    return W / nu[:, None, None]

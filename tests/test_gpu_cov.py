@@ -1,0 +1,204 @@
+"""Full-covariance likelihood (dense 3x3 per bin) on the GPU against the oracle.
+
+Data: the oracle's covariance at a truth state, then averaged complex-Wishart
+draws from the seeded generator (real parts of the six cross-periodogram
+rows).  States: the workload's diagonal-model states with three correlation
+splines appended (heights N(0, 0.5^2), 0..k in-between knots)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from oracle import covariance as CV  # noqa: E402
+from oracle import lps_oracle as O  # noqa: E402
+from synth import workloads as W  # noqa: E402
+
+REL = 1e-10   # FP64 end to end: per-bin rounding ~1e-16, summed over <= 1e6 bins
+
+
+@pytest.fixture(scope="module")
+def lps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_06300_amd as m
+    m.lib()
+    return m
+
+
+def _knots(sb, s):
+    return [sb.knots(s, j) for j in range(sb.n_spl)]
+
+
+def _setup(name, n_bins, layout, n_states, corr_inbetween=(0, 8), seed=0, corr=None):
+    ds = W.make_dataset(name, n_bins=n_bins, layout=layout)
+    x_lo, x_hi = W.band_edges(ds.f)
+    nb = ds.n_spl
+    corr = tuple(corr) if corr is not None else (nb, nb + 1, nb + 2)
+    cds = CV.CovDataset(base=ds, corr=corr, n_spl=nb + 3)
+    truth = W.append_splines(ds.truth, np.random.default_rng(50 + seed), 3, (1, 4), x_lo, x_hi, 0.5)
+    C, _, _ = CV.covariance(cds, truth.params[:, 0], _knots(truth, 0))
+    Pc = W.complex_wishart_mean(np.random.default_rng(60 + seed), C, np.rint(ds.nk))
+    P6 = CV.unique_entries(Pc.real)
+    sb = W.make_states(name, ds, n_states=n_states, seed_offset=seed)
+    sb = W.append_splines(sb, np.random.default_rng(70 + seed), 3, corr_inbetween, x_lo, x_hi, 0.5)
+    return ds, cds, P6, sb
+
+
+def _ctx(lps, ds, cds, P6, max_states):
+    return lps.CovContext(ds.f, ds.nk, P6, ds.R, ds.route, cds.corr, cds.n_spl, Rfg=ds.Rfg,
+                          max_states=max_states, f_knee=ds.f_knee, arm_length=ds.arm_length)
+
+
+def _oracle(cds, P6, sb, idx):
+    return np.array([CV.loglike(cds, P6, sb.params[:, s], _knots(sb, s)) for s in idx])
+
+
+@pytest.mark.parametrize("layout", ["paper", "split", "split_fg", "noise_signal"])
+def test_loglike_matches_oracle(lps, layout):
+    name = "avg50_1000bins_64states"
+    ds, cds, P6, sb = _setup(name, 1000, layout, 48)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    got, status = ctx.loglike_batch(st)
+    got = got.cpu().numpy()
+    want = _oracle(cds, P6, sb, range(sb.n))
+    assert np.all(status.cpu().numpy() == 0)
+    assert np.all(np.abs(got - want) <= REL * np.abs(want)), np.max(np.abs(got - want) / np.abs(want))
+
+
+def test_dense_knots_and_ragged_tail(lps):
+    """Up to 64 knots per spline: many chunks straddle pieces; K = 2497 leaves a ragged last chunk."""
+    name = "daily_2497bins_320states"
+    ds, cds, P6, sb = _setup(name, None, "paper", 24, corr_inbetween=(20, 62), seed=1)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    got = ctx.loglike_batch(st)[0].cpu().numpy()
+    want = _oracle(cds, P6, sb, range(sb.n))
+    assert np.all(np.abs(got - want) <= REL * np.abs(want))
+
+
+def test_build_matches_oracle_covariance(lps):
+    name = "avg50_1000bins_64states"
+    ds, cds, P6, sb = _setup(name, 700, "paper", 6, seed=2)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    C, status = ctx.build(st, 13, 650)
+    C = C.cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    for s in range(sb.n):
+        Co, _, _ = CV.covariance(cds, sb.params[:, s], _knots(sb, s))
+        want = CV.unique_entries(Co)[:, 13:650]
+        scale = np.sqrt(np.stack([want[a] * want[b] for (a, b) in CV.PAIRS]))
+        assert np.all(np.abs(C[s] - want) <= 1e-13 * scale)
+
+
+def test_zero_correlation_equals_the_diagonal_path(lps):
+    name = "avg50_1000bins_64states"
+    ds, cds, P6, sb = _setup(name, 1000, "paper", 16, seed=3, corr=(-1, -1, -1))
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    got = ctx.loglike_batch(st)[0].cpu().numpy()
+    dctx = lps.Context(ds.f, ds.nk, P6[:3], ds.R, ds.route, ds.n_spl, Rfg=ds.Rfg, max_states=sb.n,
+                       f_knee=ds.f_knee, arm_length=ds.arm_length)
+    base = W.pack_states(sb.params, [_knots(sb, s)[:ds.n_spl] for s in range(sb.n)], ds.n_spl)
+    dst = dctx.states(base.params, base.knot_off, base.knot_x, base.knot_y)
+    diag = dctx.loglike_batch(dst, "fp64")[0].cpu().numpy()
+    want = np.array([O.loglike(ds, P6[:3], sb.params[:, s], _knots(sb, s)[:ds.n_spl]) for s in range(sb.n)])
+    assert np.all(np.abs(got - want) <= REL * np.abs(want))
+    assert np.all(np.abs(got - diag) <= REL * np.abs(want))
+
+
+def test_result_does_not_depend_on_the_batch(lps):
+    name = "avg50_1000bins_64states"
+    ds, cds, P6, sb = _setup(name, 1000, "paper", 64, seed=4)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    full = ctx.loglike_batch(ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y))[0].cpu().numpy()
+    for idx in ([5], [63, 0, 17], list(range(20, 40))):
+        sub = W.states_subset(sb, idx)
+        got = ctx.loglike_batch(ctx.states(sub.params, sub.knot_off, sub.knot_x, sub.knot_y))[0].cpu().numpy()
+        assert np.array_equal(got, full[idx])
+
+
+def test_invalid_states_and_errors(lps):
+    name = "avg50_1000bins_64states"
+    ds, cds, P6, sb = _setup(name, 500, "paper", 1, seed=5)
+    x_lo, x_hi = W.band_edges(ds.f)
+    p = sb.params[:, 0]
+    kn = _knots(sb, 0)
+    cases = []
+    k = list(kn)
+    k[5] = (kn[5][0][::-1].copy(), kn[5][1])                      # unordered correlation knots
+    cases.append((p, k))
+    k = list(kn)
+    k[6] = (kn[6][0][:1], kn[6][1][:1])                           # one knot
+    cases.append((p, k))
+    k = list(kn)
+    k[4] = (kn[4][0], np.full(kn[4][0].size, np.inf))             # non-finite height
+    cases.append((p, k))
+    k = list(kn)
+    k[4] = (np.array([x_lo + 0.1, x_hi]), np.array([0.0, 0.0]))   # does not cover the band
+    cases.append((p, k))
+    # A and E with the same noise, negligible signal, r_AE = 1 in double: singular
+    k = list(kn)
+    k[1] = kn[0]
+    k[4] = (np.array([x_lo, x_hi]), np.array([30.0, 30.0]))
+    p2 = p.copy()
+    p2[2] = -80.0
+    cases.append((p2, k))
+    cases.append((p, kn))                                          # valid
+    params = np.stack([c[0] for c in cases], axis=1)
+    sbx = W.pack_states(params, [c[1] for c in cases], cds.n_spl)
+    want_st = np.array([CV.state_status(cds, params[:, i], cases[i][1]) for i in range(len(cases))])
+    assert list(want_st[:5] != 0) == [True] * 5 and want_st[4] == O.ST_PSD and want_st[5] == 0
+    ctx = _ctx(lps, ds, cds, P6, 8)
+    st = ctx.states(sbx.params, sbx.knot_off, sbx.knot_x, sbx.knot_y)
+    got, status = ctx.loglike_batch(st)
+    got, status = got.cpu().numpy(), status.cpu().numpy()
+    assert np.array_equal(status, want_st)
+    assert np.all(got[:5] == -math.inf)
+    want = CV.loglike(cds, P6, p, kn)
+    assert abs(got[5] - want) <= REL * abs(want)
+    # structural errors
+    with pytest.raises(lps.LpsError):
+        big = W.states_subset(sbx, [0] * 9)
+        ctx.loglike_batch(ctx.states(big.params, big.knot_off, big.knot_x, big.knot_y))
+    with pytest.raises(lps.LpsError):
+        lps.CovContext(ds.f, ds.nk, P6, ds.R, ds.route, (0, 1, 9), cds.n_spl, max_states=1)
+    with pytest.raises(lps.LpsError):
+        ctx.build(st, 10, 10)
+    empty = W.states_subset(sbx, [])
+    ctx.loglike_batch(ctx.states(empty.params, empty.knot_off, np.zeros(1), np.zeros(1)))
+
+
+def test_full_year_grid_sampled(lps):
+    """912085 one-year bins and 4096 states, in the launch configuration of the
+    benchmark; three states compared with the oracle."""
+    name = "year_912085bins_4096states"
+    ds = W.make_dataset(name, layout="paper")
+    x_lo, x_hi = W.band_edges(ds.f)
+    nb = ds.n_spl
+    cds = CV.CovDataset(base=ds, corr=(nb, nb + 1, nb + 2), n_spl=nb + 3)
+    truth = W.append_splines(ds.truth, np.random.default_rng(80), 3, (1, 4), x_lo, x_hi, 0.5)
+    C, _, _ = CV.covariance(cds, truth.params[:, 0], _knots(truth, 0))
+    P6 = CV.unique_entries(W.complex_wishart_mean(np.random.default_rng(81), C, np.rint(ds.nk)).real)
+    del C
+    sb = W.make_states(name, ds)
+    sb = W.append_splines(sb, np.random.default_rng(82), 3, (0, 30), x_lo, x_hi, 0.5)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    got, status = ctx.loglike_batch(ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y))
+    got, status = got.cpu().numpy(), status.cpu().numpy()
+    # a few drawn states overflow 10^P between close knots (PSD bit): the
+    # oracle must agree on each of them
+    flagged = list(np.nonzero(status)[0])
+    assert len(flagged) <= 8
+    for s in [0, 2049, sb.n - 1] + flagged:
+        kn = _knots(sb, s)
+        assert status[s] == CV.state_status(cds, sb.params[:, s], kn), s
+        want = CV.loglike(cds, P6, sb.params[:, s], kn)
+        if status[s]:
+            assert got[s] == want == -math.inf
+        else:
+            assert abs(got[s] - want) <= REL * abs(want), (s, got[s], want)

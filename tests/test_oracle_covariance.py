@@ -202,3 +202,20 @@ def test_invalid_states_and_a_singular_covariance():
     assert np.tanh(30.0) == 1.0
     assert CV.state_status(cds, p2, sing) == O.ST_PSD
     assert CV.loglike(cds, P6, p2, sing) == -math.inf
+
+
+def test_single_draw_wishart_mean():
+    """nu = 1 (the unaveraged periodogram): E[z z^H] = C, rank one per bin."""
+    ds = _base(50)
+    cds = _cds(ds)
+    sb = _states(ds, 1, 9)
+    C, _, _ = CV.covariance(cds, sb.params[:, 0], _knots(sb, 0))
+    rng = np.random.default_rng(10)
+    reps = 4000
+    acc = np.zeros_like(C)
+    for _ in range(reps):
+        Pc = W.complex_wishart_mean(rng, C, np.ones(ds.f.size))
+        acc += Pc.real
+    assert np.all(np.linalg.matrix_rank(Pc) == 1)
+    s = np.sqrt(np.einsum("kaa,kbb->kab", C, C))
+    assert np.all(np.abs(acc / reps - C) < 6.0 * s / math.sqrt(reps))
