@@ -93,6 +93,7 @@ def parse():
     p.add_argument("--plain-states", type=int, default=64,
                    help="states timed on the plain FP64 per-state path (per-state cost is uniform)")
     p.add_argument("--cpu-states", type=int, default=64, help="states in the CPU oracle sample")
+    p.add_argument("--cpu-cov-states", type=int, default=4, help="states in the full-covariance CPU sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-grad", action="store_true")
@@ -104,6 +105,7 @@ def parse():
                    help="sampler sweeps timed on the sweep workload (0 skips the sampler leg)")
     p.add_argument("--sweep-workload", default="sweep_250000bins_2048chains")
     p.add_argument("--no-data", action="store_true", help="skip the data-stage leg")
+    p.add_argument("--no-cov", action="store_true", help="skip the full-covariance leg")
     p.add_argument("--launch", default="",
                    help="fixed launch shapes instead of autotuning, e.g. mixed=8x128,fp64=4x64")
     return p.parse_args()
@@ -167,6 +169,100 @@ def cpu_baseline(name, n_states, dataset_bins=None):
     return {"value": len(idx) * K / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
             "sample": f"{len(idx)} of {sb.n} states x {K} bins x 3 channels of {name} "
                       f"(numpy FP64, single thread), {dt:.1f} s"}
+
+
+# Full-covariance leg: the one-year grid with the paper's layout (one noise
+# spline per channel, one signal spline) plus three correlation splines.
+COV_WORKLOAD = "year_912085bins_4096states"
+COV_LAYOUT = "paper"
+COV_CORR_INBETWEEN = (0, 30)
+# Algorithmic work per state.bin of that layout, counting an add or multiply
+# as 1, an FMA as 2 and each exp10 / sqrt / tanh / division / log as 1:
+#   7 spline cubics (1 sub + 3 FMA)                                    49
+#   power-law exponent (sub + FMA)                                      3
+#   Sn_c, Sh_c, C_cc for 3 channels                                    30
+#   vine (2 squares, products, FMA)                                     7
+#   correlation form: 1/(s0 s1 s2), Delta^-1, rho_ab                   14
+#   minors, determinant, cofactors                                     17
+#   trace numerator (scaled data, 6 products and sums)                 25
+#   logdet argument, N_k (tr + ld)                                      5
+#   exp10 x5, sqrt x7, tanh x3, division x5, log x1                    21
+COV_FLOP_PER_STATE_BIN = 171
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _cov_states(W, ds, name, rng_seed):
+    sb = W.make_states(name, ds)
+    x_lo, x_hi = W.band_edges(ds.f)
+    return W.append_splines(sb, np.random.default_rng(rng_seed), 3, COV_CORR_INBETWEEN, x_lo, x_hi, 0.5)
+
+
+def cov_bench(torch, lps, W, args, dev):
+    """Dense 3x3 covariance likelihood (FP64) of every state of the one-year workload."""
+    name = COV_WORKLOAD
+    ds = W.make_dataset(name, layout=COV_LAYOUT)
+    K = ds.f.size
+    nb = ds.n_spl
+    corr = (nb, nb + 1, nb + 2)
+    x_lo, x_hi = W.band_edges(ds.f)
+    truth = W.append_splines(ds.truth, np.random.default_rng(180), 3, (1, 4), x_lo, x_hi, 0.5)
+    # data: complex-Wishart draws around the library's own model covariance at the truth state
+    ctx0 = lps.CovContext(ds.f, ds.nk, np.ones((6, K)), ds.R, ds.route, corr, nb + 3, max_states=1, device=dev)
+    C6, _ = ctx0.build(ctx0.states(truth.params, truth.knot_off, truth.knot_x, truth.knot_y))
+    ctx0.close()
+    C6 = C6[0].cpu().numpy()
+    C = np.empty((K, 3, 3))
+    for i, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        C[:, a, b] = C6[i]
+        C[:, b, a] = C6[i]
+    Pc = W.complex_wishart_mean(np.random.default_rng(181), C, np.rint(ds.nk))
+    P6 = np.stack([Pc[:, a, b].real for (a, b) in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))])
+    del C, Pc
+    sb = _cov_states(W, ds, name, 182)
+    n = sb.n
+    ctx = lps.CovContext(ds.f, ds.nk, P6, ds.R, ds.route, corr, nb + 3, max_states=n, device=dev)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    steps = max(3, args.steps // 4)
+    t, _ = timed_graph(torch, lambda: ctx.loglike_batch(st, out=out, status=status), steps, 1)
+    per = t / steps
+    valid = int((status == 0).sum().item())
+    achieved = n * K * COV_FLOP_PER_STATE_BIN / per / 1e12
+    log(f"cov: {per * 1e3:.2f} ms/call, {n * K / per:.3e} state.bin/s, {achieved:.2f} TFLOP/s FP64 "
+        f"({achieved / PEAK_FP64_TFLOPS:.1%}); {valid}/{n} states valid")
+    ctx.close()
+    return {"workload": name, "layout": COV_LAYOUT, "n_bins": K, "n_states": n, "splines_per_state": nb + 3,
+            "correlation_in_between_knots": list(COV_CORR_INBETWEEN), "dtype": "f64",
+            "value": n * K / per, "unit": UNIT, "ms_per_call": per * 1e3, "valid_states": valid,
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                         "flop_per_state_bin": COV_FLOP_PER_STATE_BIN, "state_bins_per_launch": n * K,
+                         "timed": "whole call (coefficients + evaluation + finalize), graph replays"}}
+
+
+def cpu_baseline_cov(name, n_states):
+    """The full-covariance oracle on a few states of the same workload (CPU leg)."""
+    from oracle import covariance as CV
+    from synth import workloads as W
+    ds = W.make_dataset(name, layout=COV_LAYOUT)
+    nb = ds.n_spl
+    cds = CV.CovDataset(base=ds, corr=(nb, nb + 1, nb + 2), n_spl=nb + 3)
+    x_lo, x_hi = W.band_edges(ds.f)
+    truth = W.append_splines(ds.truth, np.random.default_rng(180), 3, (1, 4), x_lo, x_hi, 0.5)
+    C, _, _ = CV.covariance(cds, truth.params[:, 0], [truth.knots(0, j) for j in range(truth.n_spl)])
+    P6 = CV.unique_entries(W.complex_wishart_mean(np.random.default_rng(181), C, np.rint(ds.nk)).real)
+    del C
+    sb = _cov_states(W, ds, name, 182)
+    idx = list(range(min(n_states, sb.n)))
+    t0 = time.perf_counter()
+    for s in idx:
+        CV.loglike(cds, P6, sb.params[:, s], [sb.knots(s, j) for j in range(sb.n_spl)])
+    dt = time.perf_counter() - t0
+    K = ds.f.size
+    return {"value": len(idx) * K / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{len(idx)} of {sb.n} states x {K} bins (3x3 per bin) of {name}, {COV_LAYOUT} layout "
+                      f"+ 3 correlation splines (numpy FP64), {dt:.1f} s"}
 
 
 def main():
@@ -324,11 +420,18 @@ def main():
     if not args.no_data:
         result["data_stage"] = data_stage_bench(torch, lps, dev)
 
+    # --- full-covariance likelihood ----------------------------------------------------
+    if not args.no_cov:
+        result["cov"] = cov_bench(torch, lps, W, args, dev)
+
     # --- CPU oracle baseline ------------------------------------------------------
     if not args.no_cpu:
         log("cpu oracle sample ...")
         result["cpu_baseline"] = cpu_baseline(name, args.cpu_states)
         log(f"  {result['cpu_baseline']['value']:.3e} state.bin/s")
+        if not args.no_cov:
+            result["cpu_baseline"]["cov"] = cpu_baseline_cov(COV_WORKLOAD, args.cpu_cov_states)
+            log(f"  cov: {result['cpu_baseline']['cov']['value']:.3e} state.bin/s")
 
     print(json.dumps(result), flush=True)
 
