@@ -13,25 +13,32 @@
 //   C_cc = Sn_c + Sh_c,  C_ab = r_ab sqrt(Sn_a Sn_b);
 //   logL = - sum_k N_k ( tr(C_k^-1 P_k) + ln det C_k ).
 //
-// Per bin the kernel works in the correlation form C = Delta Ct Delta with
-// Delta = diag(sqrt C_cc): Ct has a unit diagonal and off-diagonal entries
-// rho_ab = r_ab sqrt(Sn_a / C_aa) sqrt(Sn_b / C_bb), so its cofactors and
-// determinant are O(1) whatever the channel levels; then
-//   tr(C^-1 P) = sum_ab adj(Ct)_ab P_ab / (Delta_a Delta_b det Ct),
-//   ln det C   = ln(C_AA C_EE C_TT det Ct),
-// and positive definiteness is Sylvester's criterion on Ct
-// (C_cc > 0, 1 - rho_AE^2 > 0, det Ct > 0).
+// Numerics (FP64 throughout).  The per-bin table is divided by a reference
+// level sigma_k (the A-channel noise at the library's reference amplitudes), so
+// every entry is O(1) whatever the units; ln det C gains 3 ln sigma_k, whose
+// N-weighted sum is a constant added once per state.  In those units the
+// kernel forms det C and the cofactors directly from Sn, C_cc and the
+// correlations,
+//   det C  = C_AA C_EE C_TT + 2 r_AE r_AT r_ET Sn_A Sn_E Sn_T
+//            - C_AA r_ET^2 Sn_E Sn_T - C_EE r_AT^2 Sn_A Sn_T - C_TT r_AE^2 Sn_A Sn_E,
+//   adj_AE = sqrt(Sn_A Sn_E) (r_AT r_ET Sn_T - r_AE C_TT)   (and cyclically),
+// so that only the three off-diagonal cofactors need a square root;
+// tr(C^-1 P) = sum_ab adj_ab P_ab / det C.  Positive definiteness is
+// Sylvester's criterion (C_AA > 0, C_AA C_EE - r_AE^2 Sn_A Sn_E > 0,
+// det C > 0).  Powers of ten and tanh use exp2 by range reduction to
+// [-1/2, 1/2] and the Taylor series of e^t to degree 13 (truncation below
+// 2^-55 relative), scaled by ldexp.
 //
-// Work decomposition (FP64 throughout): the coefficient kernel validates
-// every state and stores the cubic pieces of its splines (one wave per
-// state, one lane per piece).  The evaluation kernel gives each wave one tile
-// of states and one group of consecutive 128-bin chunks; it walks the chunks
-// and, inside each chunk, the states of its tile, so that the waves of a
-// workgroup read the same table rows (held in L1) for many states.  A
-// spline's pieces covering a chunk are found with two ballots over the
-// piece abscissae (lane = piece), usually one piece for the whole chunk, in
-// which case its coefficients are uniform loads.  Each wave keeps the sum of
-// state i of its tile in lane i; partial sums per (state, chunk group) are
+// Work decomposition: the coefficient kernel validates every state and
+// stores the cubic pieces of its splines (one wave per state, one lane per
+// piece).  In the evaluation kernel a workgroup of four waves takes one group
+// of consecutive 128-bin chunks and four tiles of states: it stages each
+// chunk's table rows in LDS once, and every wave then runs through the states
+// of its tile on them.  A spline's pieces over a chunk are found with two
+// ballots over the piece abscissae (lane = piece); usually one piece covers
+// the chunk and its coefficients are uniform loads.  Spline values go through
+// LDS so that the spline loop need not be unrolled.  Each wave keeps the sum
+// of state i of its tile in lane i; partial sums per (state, chunk group) are
 // added in a fixed order by the finalize kernel, so results do not depend on
 // the batch size.
 #include <math.h>
@@ -52,7 +59,8 @@ constexpr int kCovChunk = kWave * kCovB;    // 128 bins
 constexpr int kCovMaxTile = 16;             // states per wave
 constexpr int kCovGroups = 64;              // chunk groups per dataset (fixed by K alone)
 
-// Rows of the per-bin table [kCovRows][k_pad].
+// Rows of the per-bin table [kCovRows][k_pad]; every PSD-valued row is
+// divided by sigma_k.
 enum : int {
   kRx = 0,       // log10 f
   kRnu = 1,      // N_k (0 for padding)
@@ -66,9 +74,19 @@ enum : int {
   kCovRows = 18
 };
 
+constexpr double kLog2e = 1.442695040888963407359924681001892137426645954153;
+
+// Per-slot values of one bin: 10^P_j for a slot feeding a diagonal term,
+// tanh P_j for a correlation slot; two fixed entries stand for "no spline".
+constexpr int kSlotOne = kCovMaxSpl;        // 1 (an unperturbed diagonal term)
+constexpr int kSlotZero = kCovMaxSpl + 1;   // 0 (zero correlation)
+constexpr int kSlots = kCovMaxSpl + 2;
+
 struct CovRoute {
-  int8_t r[3][3];   // [OMS, TM, SGWB][channel] spline slot or -1
-  int8_t corr[3];   // slots of Q0, Q1, Q2 or -1
+  uint8_t g[3][3];      // [OMS, TM, SGWB][channel] slot of the factor 10^P (kSlotOne: none)
+  uint8_t gc[3];        // slots of tanh Q0, tanh Q1, tanh Q2 (kSlotZero: none)
+  uint32_t diag_mask;   // bit j: slot j feeds a diagonal term (value 10^P_j)
+  uint32_t corr_mask;   // bit j: slot j is a correlation term (value tanh P_j)
 };
 
 }  // namespace
@@ -79,7 +97,6 @@ struct lps_cov_ctx {
   int32_t n_bins, k_pad, n_chunks, chunks_per_group, n_groups;
   int32_t n_spl, n_params, k_max, max_states, has_fg;
   lps::CovRoute rt;
-  uint32_t diag_mask;   // bit j: spline slot j feeds a diagonal term
   double x_knee, x_first, x_last;
   double* tab;          // [kCovRows][k_pad]
   double* bx;           // [max_states][kCovMaxSpl][kMaxKnots] piece start abscissae
@@ -87,6 +104,8 @@ struct lps_cov_ctx {
   int32_t* npc;         // [max_states][kCovMaxSpl] pieces (0: disabled or invalid state)
   uint32_t* status;     // [max_states]
   double* partial;      // [max_states][n_groups]
+  double* sigma;        // [K] reference level sigma_k of the scaled table
+  double* c0;           // [1] 3 sum_k N_k ln sigma_k
 };
 
 namespace lps {
@@ -101,7 +120,8 @@ __device__ inline double readlane_d(double v, int l) {
 
 __global__ void k_cov_table(int K, int k_pad, const double* __restrict__ f, const double* __restrict__ nk,
                             const double* __restrict__ P, const double* __restrict__ R,
-                            const double* __restrict__ Rfg, double L, double* __restrict__ tab) {
+                            const double* __restrict__ Rfg, double L, double* __restrict__ tab,
+                            double* __restrict__ sig) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= k_pad) return;
   // padding repeats the last bin with N = 0 and no data: it adds exactly 0
@@ -109,19 +129,37 @@ __global__ void k_cov_table(int K, int k_pad, const double* __restrict__ f, cons
   const double fk = f[kk];
   double oms_ae, oms_t, tm_ae, tm_t, h;
   unit_templates(fk, L, oms_ae, oms_t, tm_ae, tm_t, h);
+  const double sigma = kRefAoms * kRefAoms * oms_ae + kRefAtm * kRefAtm * tm_ae;
+  const double is = 1.0 / sigma;
   double row[kCovRows];
   row[kRx] = log10(fk);
   row[kRnu] = k < K ? nk[kk] : 0.0;
-  row[kRomsAE] = oms_ae;
-  row[kRomsT] = oms_t;
-  row[kRtmAE] = tm_ae;
-  row[kRtmT] = tm_t;
+  row[kRomsAE] = oms_ae * is;
+  row[kRomsT] = oms_t * is;
+  row[kRtmAE] = tm_ae * is;
+  row[kRtmT] = tm_t * is;
   for (int c = 0; c < 3; ++c) {
-    row[kRsg + c] = R[c * (size_t)K + kk] * h;
-    row[kRfg + c] = Rfg ? Rfg[c * (size_t)K + kk] : 0.0;
+    row[kRsg + c] = R[c * (size_t)K + kk] * h * is;
+    row[kRfg + c] = Rfg ? Rfg[c * (size_t)K + kk] * is : 0.0;
   }
-  for (int i = 0; i < 6; ++i) row[kRP + i] = k < K ? P[i * (size_t)K + kk] : 0.0;
+  for (int i = 0; i < 6; ++i) row[kRP + i] = k < K ? P[i * (size_t)K + kk] * is : 0.0;
   for (int r = 0; r < kCovRows; ++r) tab[r * (size_t)k_pad + k] = row[r];
+  if (k < K) sig[k] = sigma;
+}
+
+// C0 = 3 sum_k N_k ln sigma_k in one block, fixed order.
+__global__ __launch_bounds__(256) void k_cov_c0(int K, const double* __restrict__ nk,
+                                                const double* __restrict__ sig, double* __restrict__ c0) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < K; k += 256) acc += nk[k] * log(sig[k]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c0[0] = 3.0 * sh[0];
 }
 
 // One wave per state: validation (every spline slot), then one lane per piece.
@@ -172,74 +210,89 @@ __device__ inline StateScal state_scalars(const double* __restrict__ params, int
   return r;
 }
 
+// 2^y: y = n + f with n = rint(y), |f| <= 1/2; e^(f ln 2) by the Taylor series
+// to degree 13 (Horner), scaled by 2^n.  Propagates NaN; saturates to 0 / inf.
+__device__ inline double exp2_d(double y) {
+  const double n = rint(y);
+  const double t = (y - n) * kLn2;
+  double p = 1.0 / 6227020800.0;       // 1/13!
+  p = fma(p, t, 1.0 / 479001600.0);    // 1/12!
+  p = fma(p, t, 1.0 / 39916800.0);
+  p = fma(p, t, 1.0 / 3628800.0);
+  p = fma(p, t, 1.0 / 362880.0);
+  p = fma(p, t, 1.0 / 40320.0);
+  p = fma(p, t, 1.0 / 5040.0);
+  p = fma(p, t, 1.0 / 720.0);
+  p = fma(p, t, 1.0 / 120.0);
+  p = fma(p, t, 1.0 / 24.0);
+  p = fma(p, t, 1.0 / 6.0);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  const int e = (int)fmax(fmin(n, 2100.0), -2100.0);
+  return ldexp(p, e);
+}
+
+__device__ inline double exp10_d(double y) { return exp2_d(y * kLog2_10); }
+
+// tanh q = sign(q) (1 - e) / (1 + e), e = exp(-2|q|)
+__device__ inline double tanh_d(double q) {
+  const double e = exp2_d(-2.0 * kLog2e * fabs(q));
+  return copysign((1.0 - e) / (1.0 + e), q);
+}
+
 struct CovPoint {
-  double d[3];   // C_cc
-  double h[3];   // sqrt(Sn_c)
+  double d[3];    // C_cc (scaled)
+  double sn[3];   // Sn_c (scaled)
   double r01, r02, r12;
 };
 
-// The model at one bin from the spline values Pv and the bin's table entries
-// (read through `row(r)`).
-template <typename Row>
-__device__ inline void cov_point(const double (&Pv)[kCovMaxSpl], int n_spl, const CovRoute& rt, uint32_t diag_mask,
-                                 const StateScal& sc, double x_knee, const Row& row, CovPoint& o) {
-  double fo[3] = {1.0, 1.0, 1.0}, ft[3] = {1.0, 1.0, 1.0}, fh[3] = {1.0, 1.0, 1.0};
-  double q[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < kCovMaxSpl; ++j) {
-    if (j >= n_spl) break;
-    if ((diag_mask >> j) & 1u) {
-      const double e = exp10(Pv[j]);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (rt.r[0][c] == j) fo[c] = e;
-        if (rt.r[1][c] == j) ft[c] = e;
-        if (rt.r[2][c] == j) fh[c] = e;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      if (rt.corr[i] == j) q[i] = Pv[j];
-  }
-  const double hf = exp10(sc.u + sc.alpha * (row(kRx) - x_knee));
+// The value of slot j at one bin: 10^P, tanh P, or P itself for an unused slot.
+__device__ inline double slot_value(double pv, int j, const CovRoute& rt) {
+  if ((rt.diag_mask >> j) & 1u) return exp10_d(pv);
+  if ((rt.corr_mask >> j) & 1u) return tanh_d(pv);
+  return pv;
+}
+
+// The model at one bin from the slot values V (read through `val(slot)`) and
+// the bin's table entries (read through `row(r)`).
+template <typename Val, typename Row>
+__device__ inline void cov_point(const Val& val, const CovRoute& rt, const StateScal& sc, double x_knee, const Row& row,
+                                 CovPoint& o) {
+  const double hf = exp10_d(sc.u + sc.alpha * (row(kRx) - x_knee));
   const double oms[3] = {row(kRomsAE), row(kRomsAE), row(kRomsT)};
   const double tm[3] = {row(kRtmAE), row(kRtmAE), row(kRtmT)};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double sn = sc.w_oms * oms[c] * fo[c] + sc.w_tm * tm[c] * ft[c];
-    const double sh = row(kRsg + c) * hf * fh[c] + row(kRfg + c) * sc.efg;
+    const double sn = sc.w_oms * oms[c] * val(rt.g[0][c]) + sc.w_tm * tm[c] * val(rt.g[1][c]);
+    const double sh = row(kRsg + c) * hf * val(rt.g[2][c]) + row(kRfg + c) * sc.efg;
     o.d[c] = sn + sh;
-    o.h[c] = sqrt(sn);
+    o.sn[c] = sn;
   }
-  o.r01 = tanh(q[0]);
-  o.r02 = tanh(q[1]);
-  o.r12 = o.r01 * o.r02 + tanh(q[2]) * sqrt((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
+  o.r01 = val(rt.gc[0]);
+  o.r02 = val(rt.gc[1]);
+  o.r12 = o.r01 * o.r02 + val(rt.gc[2]) * sqrt((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
 }
 
-// N_k (tr(C^-1 P) + ln det C) at one bin; `bad` is set where C is not
-// positive definite or the term is not finite.
+// N_k (tr(C^-1 P) + ln det C) at one bin in scaled units; `bad` is set where
+// C is not positive definite or the term is not finite.
 template <typename Row>
 __device__ inline double cov_term(const CovPoint& p, const Row& row, bool& bad) {
-  const double s0 = sqrt(p.d[0]), s1 = sqrt(p.d[1]), s2 = sqrt(p.d[2]);
-  const double inv = 1.0 / (s0 * s1 * s2);
-  const double i0 = inv * s1 * s2, i1 = inv * s0 * s2, i2 = inv * s0 * s1;
-  // sqrt(Sn_c / C_cc) by a correctly rounded division: exactly 1 when the
-  // channel has no signal, so that a unit correlation gives an exactly
-  // singular Ct
-  const double g0 = p.h[0] / s0, g1 = p.h[1] / s1, g2 = p.h[2] / s2;
-  const double a = p.r01 * g0 * g1, b = p.r02 * g0 * g2, c = p.r12 * g1 * g2;
-  const double m22 = 1.0 - a * a;
-  const double det = m22 - b * b - c * c + 2.0 * a * b * c;
-  const double m00 = 1.0 - c * c, m11 = 1.0 - b * b;
-  const double m01 = b * c - a, m02 = a * c - b, m12 = a * b - c;
-  const double num = m00 * row(kRP + 0) * (i0 * i0) + m11 * row(kRP + 1) * (i1 * i1) +
-                     m22 * row(kRP + 2) * (i2 * i2) +
-                     2.0 * (m01 * row(kRP + 3) * (i0 * i1) + m02 * row(kRP + 4) * (i0 * i2) +
-                            m12 * row(kRP + 5) * (i1 * i2));
+  const double d0 = p.d[0], d1 = p.d[1], d2 = p.d[2];
+  const double n0 = p.sn[0], n1 = p.sn[1], n2 = p.sn[2];
+  const double q01 = p.r01 * p.r01 * (n0 * n1);
+  const double q02 = p.r02 * p.r02 * (n0 * n2);
+  const double q12 = p.r12 * p.r12 * (n1 * n2);
+  const double a00 = d1 * d2 - q12, a11 = d0 * d2 - q02, a22 = d0 * d1 - q01;
+  const double det = d0 * a00 - d1 * q02 - d2 * q01 + 2.0 * (p.r01 * p.r02 * p.r12) * (n0 * n1 * n2);
+  const double a01 = sqrt(n0 * n1) * (p.r02 * p.r12 * n2 - p.r01 * d2);
+  const double a02 = sqrt(n0 * n2) * (p.r01 * p.r12 * n1 - p.r02 * d1);
+  const double a12 = sqrt(n1 * n2) * (p.r01 * p.r02 * n0 - p.r12 * d0);
+  const double num = a00 * row(kRP + 0) + a11 * row(kRP + 1) + a22 * row(kRP + 2) +
+                     2.0 * (a01 * row(kRP + 3) + a02 * row(kRP + 4) + a12 * row(kRP + 5));
   const double tr = num / det;
-  const double ld = log(p.d[0] * p.d[1] * p.d[2] * det);
-  const bool ok = p.d[0] > 0.0 && p.d[1] > 0.0 && p.d[2] > 0.0 && m22 > 0.0 && det > 0.0 && isfinite(tr) &&
-                  isfinite(ld);
+  const double ld = log(det);
+  const bool ok = d0 > 0.0 && a22 > 0.0 && det > 0.0 && isfinite(tr) && isfinite(ld);
   bad = bad || !ok;
   return row(kRnu) * (tr + ld);
 }
@@ -249,7 +302,6 @@ struct CovArgs {
   int k_pad, n_chunks, chunks_per_group, n_groups;
   int n_states, tile, n_tiles, n_spl, has_fg;
   CovRoute rt;
-  uint32_t diag_mask;
   double x_knee;
   const double* params;
   uint32_t* status;
@@ -259,6 +311,11 @@ struct CovArgs {
   double* partial;
 };
 
+struct LdsVal {
+  const double* p;   // &lval[wave][0][lane]
+  __device__ double operator()(int j) const { return p[j * kWave]; }
+};
+
 struct TabRow {
   const double* __restrict__ p;
   size_t stride;
@@ -266,73 +323,99 @@ struct TabRow {
 };
 
 __global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
+  __shared__ double lval[4][kCovB][kSlots][kWave];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = uniform(xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + (int)(threadIdx.x / kWave));
-  if (wid >= A.n_tiles * A.n_groups) return;
-  const int g = wid / A.n_tiles, t = wid - g * A.n_tiles;
+  const int w = (int)(threadIdx.x / kWave);
+  const int quads = (A.n_tiles + 3) / 4;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  if (blk >= quads * A.n_groups) return;
+  const int g = blk / quads;
+  const int t = (blk - g * quads) * 4 + w;
   const int s0 = t * A.tile;
-  const int ns = min(A.tile, A.n_states - s0);
+  const int ns = t < A.n_tiles ? min(A.tile, A.n_states - s0) : 0;
   const int c_begin = g * A.chunks_per_group;
   const int c_end = min(A.n_chunks, c_begin + A.chunks_per_group);
+  const size_t kp = (size_t)A.k_pad;
   double acc = 0.0;   // lane i: the sum of state s0 + i over this group
+#pragma unroll
+  for (int b = 0; b < kCovB; ++b) {
+    lval[w][b][kSlotOne][lane] = 1.0;
+    lval[w][b][kSlotZero][lane] = 0.0;
+  }
   for (int ch = c_begin; ch < c_end; ++ch) {
     const int kb = ch * kCovChunk;
-    const double xf = A.tab[kRx * (size_t)A.k_pad + kb];
-    const double xl = A.tab[kRx * (size_t)A.k_pad + kb + kCovChunk - 1];
+    const double* tb = A.tab + kb + lane;   // row r, bin b of the chunk: tb[r * kp + b * kWave]
+    const double xf = A.tab[kRx * kp + kb];
+    const double xl = A.tab[kRx * kp + kb + kCovChunk - 1];
+    double xb[kCovB];
+#pragma unroll
+    for (int b = 0; b < kCovB; ++b) xb[b] = tb[kRx * kp + b * kWave];
     for (int i = 0; i < ns; ++i) {
       const int s = s0 + i;
       if (A.status[s] != 0u) continue;
       const StateScal sc = state_scalars(A.params, A.n_states, s, A.has_fg);
-      // pieces of every spline over this chunk
-      int lo[kCovMaxSpl], hi[kCovMaxSpl], np[kCovMaxSpl];
-      double bl[kCovMaxSpl];
+      // slot values at the chunk's bins, two splines at a time: lane p holds
+      // piece p of each spline (start abscissa and cubic coefficients)
+#pragma unroll 1
+      for (int j0 = 0; j0 < A.n_spl; j0 += 2) {
+        int np[2];
+        double bl[2], k0[2], k1[2], k2[2], k3[2];
 #pragma unroll
-      for (int j = 0; j < kCovMaxSpl; ++j) {
-        np[j] = j < A.n_spl ? A.npc[(size_t)s * kCovMaxSpl + j] : 0;
-        lo[j] = hi[j] = 0;
-        bl[j] = 0.0;
-        if (np[j] > 0) {
-          const double* br = A.bx + ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-          bl[j] = lane < np[j] ? br[lane] : INFINITY;
-          lo[j] = max(__popcll(__ballot(bl[j] <= xf)) - 1, 0);
-          hi[j] = max(__popcll(__ballot(bl[j] <= xl)) - 1, 0);
+        for (int u = 0; u < 2; ++u) {
+          const int j = j0 + u;
+          np[u] = j < A.n_spl ? A.npc[(size_t)s * kCovMaxSpl + j] : 0;
+          const size_t r = ((size_t)s * kCovMaxSpl + j) * kMaxKnots + lane;
+          const bool mine = lane < np[u];
+          bl[u] = mine ? A.bx[r] : INFINITY;
+          k0[u] = mine ? A.coef[r * 4 + 0] : 0.0;
+          k1[u] = mine ? A.coef[r * 4 + 1] : 0.0;
+          k2[u] = mine ? A.coef[r * 4 + 2] : 0.0;
+          k3[u] = mine ? A.coef[r * 4 + 3] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int j = j0 + u;
+          if (j >= A.n_spl) break;
+          if (np[u] == 0) {
+            const double v0 = slot_value(0.0, j, A.rt);
+#pragma unroll
+            for (int b = 0; b < kCovB; ++b) lval[w][b][j][lane] = v0;
+            continue;
+          }
+          const int lo = max(__popcll(__ballot(bl[u] <= xf)) - 1, 0);
+          const int hi = max(__popcll(__ballot(bl[u] <= xl)) - 1, 0);
+#pragma unroll
+          for (int b = 0; b < kCovB; ++b) {
+            double x0, a0, a1, a2, a3;
+            if (lo == hi) {
+              x0 = readlane_d(bl[u], lo);
+              a0 = readlane_d(k0[u], lo);
+              a1 = readlane_d(k1[u], lo);
+              a2 = readlane_d(k2[u], lo);
+              a3 = readlane_d(k3[u], lo);
+            } else {
+              int pc = lo;
+              for (int q = lo + 1; q <= hi; ++q)
+                if (xb[b] >= readlane_d(bl[u], q)) pc = q;
+              x0 = __shfl(bl[u], pc, kWave);
+              a0 = __shfl(k0[u], pc, kWave);
+              a1 = __shfl(k1[u], pc, kWave);
+              a2 = __shfl(k2[u], pc, kWave);
+              a3 = __shfl(k3[u], pc, kWave);
+            }
+            const double tt = xb[b] - x0;
+            lval[w][b][j][lane] = slot_value(a0 + tt * (a1 + tt * (a2 + tt * a3)), j, A.rt);
+          }
         }
       }
       double v = 0.0;
       bool bad = false;
-#pragma unroll
+#pragma unroll 1
       for (int b = 0; b < kCovB; ++b) {
-        const int k = kb + b * kWave + lane;
-        const TabRow row{A.tab + k, (size_t)A.k_pad};
-        const double x = row(kRx);
-        double Pv[kCovMaxSpl];
-#pragma unroll
-        for (int j = 0; j < kCovMaxSpl; ++j) {
-          Pv[j] = 0.0;
-          if (np[j] == 0) continue;
-          const double* cr = A.coef + ((size_t)s * kCovMaxSpl + j) * kMaxKnots * 4;
-          double x0, c0, c1, c2, c3;
-          if (lo[j] == hi[j]) {
-            x0 = readlane_d(bl[j], lo[j]);
-            c0 = cr[lo[j] * 4 + 0];
-            c1 = cr[lo[j] * 4 + 1];
-            c2 = cr[lo[j] * 4 + 2];
-            c3 = cr[lo[j] * 4 + 3];
-          } else {
-            int pc = lo[j];
-            for (int p = lo[j] + 1; p <= hi[j]; ++p)
-              if (x >= readlane_d(bl[j], p)) pc = p;
-            x0 = __shfl(bl[j], pc, kWave);
-            c0 = cr[pc * 4 + 0];
-            c1 = cr[pc * 4 + 1];
-            c2 = cr[pc * 4 + 2];
-            c3 = cr[pc * 4 + 3];
-          }
-          const double tt = x - x0;
-          Pv[j] = c0 + tt * (c1 + tt * (c2 + tt * c3));
-        }
+        const TabRow row{tb + b * kWave, kp};
+        const LdsVal val{&lval[w][b][0][lane]};
         CovPoint p;
-        cov_point(Pv, A.n_spl, A.rt, A.diag_mask, sc, A.x_knee, row, p);
+        cov_point(val, A.rt, sc, A.x_knee, row, p);
         v += cov_term(p, row, bad);
       }
       if (__ballot(bad) != 0ull && lane == 0) atomicOr(&A.status[s], (unsigned)LPS_ST_PSD);
@@ -344,24 +427,25 @@ __global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
 }
 
 __global__ void k_cov_finalize(int n_states, int n_groups, const double* __restrict__ partial,
-                               const uint32_t* __restrict__ status, double* __restrict__ logL,
-                               uint32_t* __restrict__ status_out) {
+                               const double* __restrict__ c0, const uint32_t* __restrict__ status,
+                               double* __restrict__ logL, uint32_t* __restrict__ status_out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_states) return;
   const uint32_t st = status[s];
   double sum = 0.0;
   for (int g = 0; g < n_groups; ++g) sum += partial[(size_t)s * n_groups + g];
-  logL[s] = st ? -INFINITY : -sum;
+  logL[s] = st ? -INFINITY : -(sum + c0[0]);
   if (status_out) status_out[s] = st;
 }
 
 // The six unique entries of C for bins [k0, k1) of every state (binary search
 // for the piece of each bin).
 __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const double* __restrict__ tab, int n_spl,
-                            CovRoute rt, uint32_t diag_mask, double x_knee, int has_fg,
+                            CovRoute rt, double x_knee, int has_fg,
                             const double* __restrict__ params, const uint32_t* __restrict__ status,
                             const double* __restrict__ bx, const double* __restrict__ coef,
-                            const int32_t* __restrict__ npc, double* __restrict__ C) {
+                            const int32_t* __restrict__ npc, const double* __restrict__ sigma,
+                            double* __restrict__ C) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)n_states * n_out) return;
   const int s = (int)(i / n_out), q = (int)(i % n_out), k = k0 + q;
@@ -372,11 +456,16 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
   }
   const TabRow row{tab + k, (size_t)k_pad};
   const double x = row(kRx);
-  double Pv[kCovMaxSpl];
+  double V[kSlots];
+  V[kSlotOne] = 1.0;
+  V[kSlotZero] = 0.0;
   for (int j = 0; j < kCovMaxSpl; ++j) {
-    Pv[j] = 0.0;
+    V[j] = 0.0;
     const int n = j < n_spl ? npc[(size_t)s * kCovMaxSpl + j] : 0;
-    if (n == 0) continue;
+    if (n == 0) {
+      V[j] = slot_value(0.0, j, rt);
+      continue;
+    }
     const double* br = bx + ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
     int lo = 0, hi = n - 1;   // last piece whose start is <= x, clamped to [0, n-1]
     while (lo < hi) {
@@ -386,15 +475,17 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
     }
     const double* cr = coef + (((size_t)s * kCovMaxSpl + j) * kMaxKnots + lo) * 4;
     const double tt = x - br[lo];
-    Pv[j] = cr[0] + tt * (cr[1] + tt * (cr[2] + tt * cr[3]));
+    V[j] = slot_value(cr[0] + tt * (cr[1] + tt * (cr[2] + tt * cr[3])), j, rt);
   }
   const StateScal sc = state_scalars(params, n_states, s, has_fg);
   CovPoint p;
-  cov_point(Pv, n_spl, rt, diag_mask, sc, x_knee, row, p);
+  cov_point([&](int j) { return V[j]; }, rt, sc, x_knee, row, p);
   const double r[3] = {p.r01, p.r02, p.r12};
   const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-  for (int c = 0; c < 3; ++c) out[(size_t)c * n_out] = p.d[c];
-  for (int e = 0; e < 3; ++e) out[(size_t)(3 + e) * n_out] = p.h[pa[e]] * r[e] * p.h[pb[e]];
+  const double sg = sigma[k];
+  for (int c = 0; c < 3; ++c) out[(size_t)c * n_out] = p.d[c] * sg;
+  for (int e = 0; e < 3; ++e)
+    out[(size_t)(3 + e) * n_out] = sqrt(p.sn[pa[e]]) * r[e] * sqrt(p.sn[pb[e]]) * sg;
 }
 
 lps_status check_cov_states(const lps_cov_ctx* ctx, const lps_states* st) {
@@ -465,10 +556,19 @@ lps_status lps_cov_create(const lps_cov_desc* d, int device, lps_cov_ctx** out) 
   c->max_states = d->max_states;
   for (int t = 0; t < 3; ++t)
     for (int ch = 0; ch < 3; ++ch) {
-      c->rt.r[t][ch] = d->route[t][ch];
-      if (d->route[t][ch] >= 0) c->diag_mask |= 1u << d->route[t][ch];
+      const int j = d->route[t][ch];
+      c->rt.g[t][ch] = (uint8_t)(j >= 0 ? j : kSlotOne);
+      if (j >= 0) c->rt.diag_mask |= 1u << j;
     }
-  for (int i = 0; i < 3; ++i) c->rt.corr[i] = d->corr[i];
+  for (int i = 0; i < 3; ++i) {
+    const int j = d->corr[i];
+    c->rt.gc[i] = (uint8_t)(j >= 0 ? j : kSlotZero);
+    if (j >= 0) c->rt.corr_mask |= 1u << j;
+  }
+  if (c->rt.diag_mask & c->rt.corr_mask) {
+    delete c;
+    return LPS_E_ROUTING;
+  }
   c->x_knee = log10(d->f_knee);
   c->x_first = log10(fh[0]);
   c->x_last = log10(fh[K - 1]);
@@ -480,12 +580,15 @@ lps_status lps_cov_create(const lps_cov_desc* d, int device, lps_cov_ctx** out) 
   ok = ok && hipMalloc((void**)&c->npc, S * kCovMaxSpl * sizeof(int32_t)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->status, S * sizeof(uint32_t)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->partial, S * c->n_groups * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->sigma, (size_t)K * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->c0, sizeof(double)) == hipSuccess;
   if (!ok) {
     lps_cov_destroy(c);
     return LPS_E_NOMEM;
   }
   hipLaunchKernelGGL(k_cov_table, dim3((c->k_pad + 255) / 256), dim3(256), 0, 0, K, c->k_pad, d->f, d->nk, d->P,
-                     d->R, d->Rfg, d->arm_length, c->tab);
+                     d->R, d->Rfg, d->arm_length, c->tab, c->sigma);
+  hipLaunchKernelGGL(k_cov_c0, dim3(1), dim3(256), 0, 0, K, d->nk, c->sigma, c->c0);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -500,7 +603,7 @@ lps_status lps_cov_destroy(lps_cov_ctx* c) {
   if (!c) return LPS_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->tab, c->bx, c->coef, c->npc, c->status, c->partial};
+  void* ptrs[] = {c->tab, c->bx, c->coef, c->npc, c->status, c->partial, c->sigma, c->c0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -530,7 +633,6 @@ lps_status lps_cov_loglike_batch(lps_cov_ctx* c, const lps_states* st, double* l
   A.n_spl = c->n_spl;
   A.has_fg = c->has_fg;
   A.rt = c->rt;
-  A.diag_mask = c->diag_mask;
   A.x_knee = c->x_knee;
   A.params = st->params;
   A.status = c->status;
@@ -538,12 +640,12 @@ lps_status lps_cov_loglike_batch(lps_cov_ctx* c, const lps_states* st, double* l
   A.coef = c->coef;
   A.npc = c->npc;
   A.partial = c->partial;
-  const long waves = (long)A.n_tiles * A.n_groups;
-  hipLaunchKernelGGL(k_cov_eval, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A);
+  const long blocks = (long)((A.n_tiles + 3) / 4) * A.n_groups;
+  hipLaunchKernelGGL(k_cov_eval, dim3((unsigned)blocks), dim3(256), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return device_status(e);
-  hipLaunchKernelGGL(k_cov_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, c->n_groups, c->partial, c->status,
-                     logL, status);
+  hipLaunchKernelGGL(k_cov_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, c->n_groups, c->partial, c->c0,
+                     c->status, logL, status);
   return device_status(hipGetLastError());
 }
 
@@ -562,8 +664,8 @@ lps_status lps_cov_build(lps_cov_ctx* c, const lps_states* st, int32_t k0, int32
   const int n_out = k1 - k0;
   const long total = (long)n * n_out;
   hipLaunchKernelGGL(k_cov_build, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, k0, n_out, c->k_pad,
-                     c->tab, c->n_spl, c->rt, c->diag_mask, c->x_knee, c->has_fg, st->params, c->status, c->bx,
-                     c->coef, c->npc, C);
+                     c->tab, c->n_spl, c->rt, c->x_knee, c->has_fg, st->params, c->status, c->bx,
+                     c->coef, c->npc, c->sigma, C);
   e = hipGetLastError();
   if (e == hipSuccess && status)
     e = hipMemcpyAsync(status, c->status, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
