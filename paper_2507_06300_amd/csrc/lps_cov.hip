@@ -322,8 +322,29 @@ struct TabRow {
   __device__ double operator()(int r) const { return p[r * stride]; }
 };
 
+// The piece of spline (s, j) that holds a bin and the start of the next one.
+struct PieceRec {
+  double x0, a0, a1, a2, a3, xn;
+};
+
+__device__ inline PieceRec load_piece(const CovArgs& A, size_t row, int q, int np) {
+  PieceRec p;
+  p.x0 = A.bx[row + q];
+  const double* c = A.coef + (row + q) * 4;
+  p.a0 = c[0];
+  p.a1 = c[1];
+  p.a2 = c[2];
+  p.a3 = c[3];
+  p.xn = q + 1 < np ? A.bx[row + q + 1] : INFINITY;
+  return p;
+}
+
 __global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
-  __shared__ double lval[4][kCovB][kSlots][kWave];
+  // per wave: slot values of the current bin, and for every (state, spline) of
+  // its tile the piece under the cursor (cursor, last piece this chunk, pieces)
+  __shared__ double lval[4][kSlots][kWave];
+  __shared__ PieceRec lrec[4][kCovMaxTile][kCovMaxSpl];
+  __shared__ int lcur[4][kCovMaxTile][kCovMaxSpl][3];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = (int)(threadIdx.x / kWave);
   const int quads = (A.n_tiles + 3) / 4;
@@ -336,87 +357,96 @@ __global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
   const int c_begin = g * A.chunks_per_group;
   const int c_end = min(A.n_chunks, c_begin + A.chunks_per_group);
   const size_t kp = (size_t)A.k_pad;
-  double acc = 0.0;   // lane i: the sum of state s0 + i over this group
-#pragma unroll
-  for (int b = 0; b < kCovB; ++b) {
-    lval[w][b][kSlotOne][lane] = 1.0;
-    lval[w][b][kSlotZero][lane] = 0.0;
+  lval[w][kSlotOne][lane] = 1.0;
+  lval[w][kSlotZero][lane] = 0.0;
+  const LdsVal val{&lval[w][0][lane]};
+
+  // cursors at the first bin of the group (lane = piece)
+  const double xg = A.tab[kRx * kp + (size_t)c_begin * kCovChunk];
+  for (int i = 0; i < ns; ++i) {
+    const int s = s0 + i;
+    if (A.status[s] != 0u) continue;
+#pragma unroll 1
+    for (int j = 0; j < A.n_spl; ++j) {
+      const int np = A.npc[(size_t)s * kCovMaxSpl + j];
+      int cur = -1;
+      if (np > 0) {
+        const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
+        const double bl = lane < np ? A.bx[row + lane] : INFINITY;
+        cur = uniform(max(__popcll(__ballot(bl <= xg)) - 1, 0));
+        const PieceRec pr = load_piece(A, row, cur, np);
+        if (lane == 0) lrec[w][i][j] = pr;
+      }
+      if (lane == 0) {
+        lcur[w][i][j][0] = cur;
+        lcur[w][i][j][1] = cur;
+        lcur[w][i][j][2] = np;
+      }
+    }
   }
+
+  double acc = 0.0;   // lane i: the sum of state s0 + i over this group
   for (int ch = c_begin; ch < c_end; ++ch) {
     const int kb = ch * kCovChunk;
     const double* tb = A.tab + kb + lane;   // row r, bin b of the chunk: tb[r * kp + b * kWave]
-    const double xf = A.tab[kRx * kp + kb];
     const double xl = A.tab[kRx * kp + kb + kCovChunk - 1];
-    double xb[kCovB];
-#pragma unroll
-    for (int b = 0; b < kCovB; ++b) xb[b] = tb[kRx * kp + b * kWave];
     for (int i = 0; i < ns; ++i) {
       const int s = s0 + i;
       if (A.status[s] != 0u) continue;
       const StateScal sc = state_scalars(A.params, A.n_states, s, A.has_fg);
-      // slot values at the chunk's bins, two splines at a time: lane p holds
-      // piece p of each spline (start abscissa and cubic coefficients)
+      // pieces that start inside this chunk
 #pragma unroll 1
-      for (int j0 = 0; j0 < A.n_spl; j0 += 2) {
-        int np[2];
-        double bl[2], k0[2], k1[2], k2[2], k3[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int j = j0 + u;
-          np[u] = j < A.n_spl ? A.npc[(size_t)s * kCovMaxSpl + j] : 0;
-          const size_t r = ((size_t)s * kCovMaxSpl + j) * kMaxKnots + lane;
-          const bool mine = lane < np[u];
-          bl[u] = mine ? A.bx[r] : INFINITY;
-          k0[u] = mine ? A.coef[r * 4 + 0] : 0.0;
-          k1[u] = mine ? A.coef[r * 4 + 1] : 0.0;
-          k2[u] = mine ? A.coef[r * 4 + 2] : 0.0;
-          k3[u] = mine ? A.coef[r * 4 + 3] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int j = j0 + u;
-          if (j >= A.n_spl) break;
-          if (np[u] == 0) {
-            const double v0 = slot_value(0.0, j, A.rt);
-#pragma unroll
-            for (int b = 0; b < kCovB; ++b) lval[w][b][j][lane] = v0;
-            continue;
-          }
-          const int lo = max(__popcll(__ballot(bl[u] <= xf)) - 1, 0);
-          const int hi = max(__popcll(__ballot(bl[u] <= xl)) - 1, 0);
-#pragma unroll
-          for (int b = 0; b < kCovB; ++b) {
-            double x0, a0, a1, a2, a3;
-            if (lo == hi) {
-              x0 = readlane_d(bl[u], lo);
-              a0 = readlane_d(k0[u], lo);
-              a1 = readlane_d(k1[u], lo);
-              a2 = readlane_d(k2[u], lo);
-              a3 = readlane_d(k3[u], lo);
-            } else {
-              int pc = lo;
-              for (int q = lo + 1; q <= hi; ++q)
-                if (xb[b] >= readlane_d(bl[u], q)) pc = q;
-              x0 = __shfl(bl[u], pc, kWave);
-              a0 = __shfl(k0[u], pc, kWave);
-              a1 = __shfl(k1[u], pc, kWave);
-              a2 = __shfl(k2[u], pc, kWave);
-              a3 = __shfl(k3[u], pc, kWave);
-            }
-            const double tt = xb[b] - x0;
-            lval[w][b][j][lane] = slot_value(a0 + tt * (a1 + tt * (a2 + tt * a3)), j, A.rt);
-          }
-        }
+      for (int j = 0; j < A.n_spl; ++j) {
+        const int cur = uniform(lcur[w][i][j][0]);
+        if (cur < 0 || !(xl >= lrec[w][i][j].xn)) continue;
+        const int np = uniform(lcur[w][i][j][2]);
+        const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
+        int hi = cur + 1;
+        while (hi + 1 < np && A.bx[row + hi + 1] <= xl) ++hi;
+        if (lane == 0) lcur[w][i][j][1] = hi;
       }
       double v = 0.0;
       bool bad = false;
 #pragma unroll 1
       for (int b = 0; b < kCovB; ++b) {
+        const double x = tb[kRx * kp + b * kWave];
+#pragma unroll 1
+        for (int j = 0; j < A.n_spl; ++j) {
+          const int cur = uniform(lcur[w][i][j][0]);
+          double pv = 0.0;
+          if (cur >= 0) {
+            PieceRec pr = lrec[w][i][j];
+            const int hi = uniform(lcur[w][i][j][1]);
+            if (hi != cur) {
+              const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
+              const int np = uniform(lcur[w][i][j][2]);
+              for (int q = cur + 1; q <= hi; ++q) {
+                const PieceRec nq = load_piece(A, row, q, np);
+                if (x >= nq.x0) pr = nq;
+              }
+            }
+            const double tt = x - pr.x0;
+            pv = pr.a0 + tt * (pr.a1 + tt * (pr.a2 + tt * pr.a3));
+          }
+          lval[w][j][lane] = slot_value(pv, j, A.rt);
+        }
         const TabRow row{tb + b * kWave, kp};
-        const LdsVal val{&lval[w][b][0][lane]};
         CovPoint p;
         cov_point(val, A.rt, sc, A.x_knee, row, p);
         v += cov_term(p, row, bad);
+      }
+      // move the cursors to the piece of the chunk's last bin
+#pragma unroll 1
+      for (int j = 0; j < A.n_spl; ++j) {
+        const int cur = uniform(lcur[w][i][j][0]);
+        const int hi = uniform(lcur[w][i][j][1]);
+        if (hi == cur) continue;
+        const int np = uniform(lcur[w][i][j][2]);
+        const PieceRec pr = load_piece(A, ((size_t)s * kCovMaxSpl + j) * kMaxKnots, hi, np);
+        if (lane == 0) {
+          lrec[w][i][j] = pr;
+          lcur[w][i][j][0] = hi;
+        }
       }
       if (__ballot(bad) != 0ull && lane == 0) atomicOr(&A.status[s], (unsigned)LPS_ST_PSD);
       v = wave_sum(v);
