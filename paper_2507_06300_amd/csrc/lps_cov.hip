@@ -87,6 +87,7 @@ struct CovRoute {
   uint8_t gc[3];        // slots of tanh Q0, tanh Q1, tanh Q2 (kSlotZero: none)
   uint32_t diag_mask;   // bit j: slot j feeds a diagonal term (value 10^P_j)
   uint32_t corr_mask;   // bit j: slot j is a correlation term (value tanh P_j)
+  int32_t sg_slot;      // slot carrying the background in all channels and nothing else, or -1
 };
 
 }  // namespace
@@ -210,22 +211,31 @@ __device__ inline StateScal state_scalars(const double* __restrict__ params, int
   return r;
 }
 
+// v_fma_f64 with every operand in a register.  (Written out because the
+// compiler otherwise turns a Horner step with a constant addend into a move
+// plus a two-address fmac.)
+__device__ inline double fma3(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // 2^y: y = n + f with n = rint(y), |f| <= 1/2; e^(f ln 2) by the Taylor series
 // to degree 13 (Horner), scaled by 2^n.  Propagates NaN; saturates to 0 / inf.
 __device__ inline double exp2_d(double y) {
   const double n = rint(y);
   const double t = (y - n) * kLn2;
-  double p = 1.0 / 6227020800.0;       // 1/13!
-  p = fma(p, t, 1.0 / 479001600.0);    // 1/12!
-  p = fma(p, t, 1.0 / 39916800.0);
-  p = fma(p, t, 1.0 / 3628800.0);
-  p = fma(p, t, 1.0 / 362880.0);
-  p = fma(p, t, 1.0 / 40320.0);
-  p = fma(p, t, 1.0 / 5040.0);
-  p = fma(p, t, 1.0 / 720.0);
-  p = fma(p, t, 1.0 / 120.0);
-  p = fma(p, t, 1.0 / 24.0);
-  p = fma(p, t, 1.0 / 6.0);
+  double p = 1.0 / 6227020800.0;          // 1/13!
+  p = fma3(p, t, 1.0 / 479001600.0);      // 1/12!
+  p = fma3(p, t, 1.0 / 39916800.0);
+  p = fma3(p, t, 1.0 / 3628800.0);
+  p = fma3(p, t, 1.0 / 362880.0);
+  p = fma3(p, t, 1.0 / 40320.0);
+  p = fma3(p, t, 1.0 / 5040.0);
+  p = fma3(p, t, 1.0 / 720.0);
+  p = fma3(p, t, 1.0 / 120.0);
+  p = fma3(p, t, 1.0 / 24.0);
+  p = fma3(p, t, 1.0 / 6.0);
   p = fma(p, t, 0.5);
   p = fma(p, t, 1.0);
   p = fma(p, t, 1.0);
@@ -235,10 +245,68 @@ __device__ inline double exp2_d(double y) {
 
 __device__ inline double exp10_d(double y) { return exp2_d(y * kLog2_10); }
 
-// tanh q = sign(q) (1 - e) / (1 + e), e = exp(-2|q|)
+// 1/a for a normal positive a: hardware estimate, two Newton steps and a
+// residual correction (within an ulp or two).
+__device__ inline double rcp_d(double a) {
+  double q = __builtin_amdgcn_rcp(a);
+  q = fma(fma(-a, q, 1.0), q, q);
+  q = fma(fma(-a, q, 1.0), q, q);
+  return q;
+}
+
+// tanh q = sign(q) (1 - e) / (1 + e), e = exp(-2|q|) in (0, 1]
 __device__ inline double tanh_d(double q) {
   const double e = exp2_d(-2.0 * kLog2e * fabs(q));
-  return copysign((1.0 - e) / (1.0 + e), q);
+  const double den = 1.0 + e, num = 1.0 - e;
+  const double r = rcp_d(den);
+  const double t = num * r;
+  return copysign(fma(fma(-den, t, num), r, t), q);
+}
+
+// sqrt x for x >= 0 (0 for x = 0): hardware reciprocal square root estimate,
+// one coupled Newton step for sqrt and 1/(2 sqrt), and a residual correction.
+__device__ inline double sqrt_d(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : (x == 0.0 ? 0.0 : NAN);
+}
+
+// ln x for a positive normal x: x = m 2^e with m in [1/sqrt2, sqrt2),
+// ln m = 2 atanh s, s = (m - 1)/(m + 1), |s| < 0.172, by its odd series to
+// s^21 (truncation below 2^-56 relative); e ln 2 with a two-part ln 2 whose
+// leading part has trailing zero bits (exact products for |e| < 2^11).
+// Non-positive or non-finite x gives NaN (the caller flags the bin).
+__device__ inline double log_d(double x) {
+  int e = __builtin_amdgcn_frexp_exp(x);
+  double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double num = m - 1.0, den = m + 1.0;
+  const double r = rcp_d(den);
+  double sv = num * r;
+  sv = fma(fma(-den, sv, num), r, sv);
+  const double z = sv * sv;
+  double p = 2.0 / 21.0;
+  p = fma3(p, z, 2.0 / 19.0);
+  p = fma3(p, z, 2.0 / 17.0);
+  p = fma3(p, z, 2.0 / 15.0);
+  p = fma3(p, z, 2.0 / 13.0);
+  p = fma3(p, z, 2.0 / 11.0);
+  p = fma3(p, z, 2.0 / 9.0);
+  p = fma3(p, z, 2.0 / 7.0);
+  p = fma3(p, z, 2.0 / 5.0);
+  p = fma3(p, z, 2.0 / 3.0);
+  const double lm = fma(sv * z, p, 2.0 * sv);
+  const double fe = (double)e;
+  const double res = fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, lm));
+  return x > 0.0 && x < INFINITY ? res : NAN;
 }
 
 struct CovPoint {
@@ -248,7 +316,11 @@ struct CovPoint {
 };
 
 // The value of slot j at one bin: 10^P, tanh P, or P itself for an unused slot.
-__device__ inline double slot_value(double pv, int j, const CovRoute& rt) {
+// lin = u + alpha (x - log10 f_knee) is added to the exponent of the slot that
+// carries the background in every channel (rt.sg_slot), which then holds the
+// whole background factor 10^(u + alpha (x - x_knee) + P).
+__device__ inline double slot_value(double pv, int j, const CovRoute& rt, double lin) {
+  if (j == rt.sg_slot) return exp10_d(pv + lin);
   if ((rt.diag_mask >> j) & 1u) return exp10_d(pv);
   if ((rt.corr_mask >> j) & 1u) return tanh_d(pv);
   return pv;
@@ -259,7 +331,7 @@ __device__ inline double slot_value(double pv, int j, const CovRoute& rt) {
 template <typename Val, typename Row>
 __device__ inline void cov_point(const Val& val, const CovRoute& rt, const StateScal& sc, double x_knee, const Row& row,
                                  CovPoint& o) {
-  const double hf = exp10_d(sc.u + sc.alpha * (row(kRx) - x_knee));
+  const double hf = rt.sg_slot >= 0 ? 1.0 : exp10_d(sc.u + sc.alpha * (row(kRx) - x_knee));
   const double oms[3] = {row(kRomsAE), row(kRomsAE), row(kRomsT)};
   const double tm[3] = {row(kRtmAE), row(kRtmAE), row(kRtmT)};
 #pragma unroll
@@ -271,7 +343,7 @@ __device__ inline void cov_point(const Val& val, const CovRoute& rt, const State
   }
   o.r01 = val(rt.gc[0]);
   o.r02 = val(rt.gc[1]);
-  o.r12 = o.r01 * o.r02 + val(rt.gc[2]) * sqrt((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
+  o.r12 = o.r01 * o.r02 + val(rt.gc[2]) * sqrt_d((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
 }
 
 // N_k (tr(C^-1 P) + ln det C) at one bin in scaled units; `bad` is set where
@@ -285,13 +357,13 @@ __device__ inline double cov_term(const CovPoint& p, const Row& row, bool& bad) 
   const double q12 = p.r12 * p.r12 * (n1 * n2);
   const double a00 = d1 * d2 - q12, a11 = d0 * d2 - q02, a22 = d0 * d1 - q01;
   const double det = d0 * a00 - d1 * q02 - d2 * q01 + 2.0 * (p.r01 * p.r02 * p.r12) * (n0 * n1 * n2);
-  const double a01 = sqrt(n0 * n1) * (p.r02 * p.r12 * n2 - p.r01 * d2);
-  const double a02 = sqrt(n0 * n2) * (p.r01 * p.r12 * n1 - p.r02 * d1);
-  const double a12 = sqrt(n1 * n2) * (p.r01 * p.r02 * n0 - p.r12 * d0);
+  const double a01 = sqrt_d(n0 * n1) * (p.r02 * p.r12 * n2 - p.r01 * d2);
+  const double a02 = sqrt_d(n0 * n2) * (p.r01 * p.r12 * n1 - p.r02 * d1);
+  const double a12 = sqrt_d(n1 * n2) * (p.r01 * p.r02 * n0 - p.r12 * d0);
   const double num = a00 * row(kRP + 0) + a11 * row(kRP + 1) + a22 * row(kRP + 2) +
                      2.0 * (a01 * row(kRP + 3) + a02 * row(kRP + 4) + a12 * row(kRP + 5));
   const double tr = num / det;
-  const double ld = log(det);
+  const double ld = log_d(det);
   const bool ok = d0 > 0.0 && a22 > 0.0 && det > 0.0 && isfinite(tr) && isfinite(ld);
   bad = bad || !ok;
   return row(kRnu) * (tr + ld);
@@ -410,6 +482,7 @@ __global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
 #pragma unroll 1
       for (int b = 0; b < kCovB; ++b) {
         const double x = tb[kRx * kp + b * kWave];
+        const double lin = sc.u + sc.alpha * (x - A.x_knee);
 #pragma unroll 1
         for (int j = 0; j < A.n_spl; ++j) {
           const int cur = uniform(lcur[w][i][j][0]);
@@ -428,7 +501,7 @@ __global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
             const double tt = x - pr.x0;
             pv = pr.a0 + tt * (pr.a1 + tt * (pr.a2 + tt * pr.a3));
           }
-          lval[w][j][lane] = slot_value(pv, j, A.rt);
+          lval[w][j][lane] = slot_value(pv, j, A.rt, lin);
         }
         const TabRow row{tb + b * kWave, kp};
         CovPoint p;
@@ -486,6 +559,8 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
   }
   const TabRow row{tab + k, (size_t)k_pad};
   const double x = row(kRx);
+  const StateScal sc = state_scalars(params, n_states, s, has_fg);
+  const double lin = sc.u + sc.alpha * (x - x_knee);
   double V[kSlots];
   V[kSlotOne] = 1.0;
   V[kSlotZero] = 0.0;
@@ -493,7 +568,7 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
     V[j] = 0.0;
     const int n = j < n_spl ? npc[(size_t)s * kCovMaxSpl + j] : 0;
     if (n == 0) {
-      V[j] = slot_value(0.0, j, rt);
+      V[j] = slot_value(0.0, j, rt, lin);
       continue;
     }
     const double* br = bx + ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
@@ -505,9 +580,8 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
     }
     const double* cr = coef + (((size_t)s * kCovMaxSpl + j) * kMaxKnots + lo) * 4;
     const double tt = x - br[lo];
-    V[j] = slot_value(cr[0] + tt * (cr[1] + tt * (cr[2] + tt * cr[3])), j, rt);
+    V[j] = slot_value(cr[0] + tt * (cr[1] + tt * (cr[2] + tt * cr[3])), j, rt, lin);
   }
-  const StateScal sc = state_scalars(params, n_states, s, has_fg);
   CovPoint p;
   cov_point([&](int j) { return V[j]; }, rt, sc, x_knee, row, p);
   const double r[3] = {p.r01, p.r02, p.r12};
@@ -515,7 +589,7 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
   const double sg = sigma[k];
   for (int c = 0; c < 3; ++c) out[(size_t)c * n_out] = p.d[c] * sg;
   for (int e = 0; e < 3; ++e)
-    out[(size_t)(3 + e) * n_out] = sqrt(p.sn[pa[e]]) * r[e] * sqrt(p.sn[pb[e]]) * sg;
+    out[(size_t)(3 + e) * n_out] = sqrt_d(p.sn[pa[e]]) * r[e] * sqrt_d(p.sn[pb[e]]) * sg;
 }
 
 lps_status check_cov_states(const lps_cov_ctx* ctx, const lps_states* st) {
@@ -598,6 +672,14 @@ lps_status lps_cov_create(const lps_cov_desc* d, int device, lps_cov_ctx** out) 
   if (c->rt.diag_mask & c->rt.corr_mask) {
     delete c;
     return LPS_E_ROUTING;
+  }
+  c->rt.sg_slot = -1;
+  {
+    const int j = d->route[LPS_TERM_SGWB][0];
+    bool only = j >= 0 && d->route[LPS_TERM_SGWB][1] == j && d->route[LPS_TERM_SGWB][2] == j;
+    for (int t = 0; t < 2 && only; ++t)
+      for (int ch = 0; ch < 3; ++ch) only = only && d->route[t][ch] != j;
+    if (only) c->rt.sg_slot = j;
   }
   c->x_knee = log10(d->f_knee);
   c->x_first = log10(fh[0]);
