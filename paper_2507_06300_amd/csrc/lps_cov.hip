@@ -56,7 +56,7 @@ namespace {
 constexpr int kCovMaxSpl = LPS_COV_MAX_SPLINES;
 constexpr int kCovB = 2;                    // bins per lane in one chunk
 constexpr int kCovChunk = kWave * kCovB;    // 128 bins
-constexpr int kCovMaxTile = 16;             // states per wave
+constexpr int kCovMaxTile = 8;              // states per wave
 constexpr int kCovGroups = 64;              // chunk groups per dataset (fixed by K alone)
 
 // Rows of the per-bin table [kCovRows][k_pad]; every PSD-valued row is
@@ -411,7 +411,9 @@ __device__ inline PieceRec load_piece(const CovArgs& A, size_t row, int q, int n
   return p;
 }
 
-__global__ __launch_bounds__(256) void k_cov_eval(CovArgs A) {
+// Four waves per SIMD: the register budget of 128 costs a few spills to
+// scratch but hides more latency than three waves without them.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_cov_eval(CovArgs A) {
   // per wave: slot values of the current bin, and for every (state, spline) of
   // its tile the piece under the cursor (cursor, last piece this chunk, pieces)
   __shared__ double lval[4][kSlots][kWave];
