@@ -189,6 +189,32 @@ COV_CORR_INBETWEEN = (0, 30)
 #   exp10 x5, sqrt x7, tanh x3, division x5, log x1                    21
 COV_FLOP_PER_STATE_BIN = 171
 PEAK_FP64_TFLOPS = 78.6
+# FP64 VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 FP64 instruction per
+# SIMD every 4 cycles.
+PEAK_FP64_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
+COV_SOURCES = ["paper_2507_06300_amd/csrc/lps_cov.hip", "paper_2507_06300_amd/csrc/lps_templates.hpp"]
+COV_PROFILE = "profiles/k_cov_eval_year_912085bins_4096states.md"
+
+
+def profiled_cov_valu():
+    """VALU lane-instructions per state.bin of the covariance kernel from the
+    committed counter summary, or None if the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, COV_PROFILE)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in COV_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    ") and "_" in line.split(":")[0]:
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("cov_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    v = fields.get("valu_lane_instr_per_state_bin")
+    return float(v) if v else None
 
 
 def _cov_states(W, ds, name, rng_seed):
@@ -232,13 +258,16 @@ def cov_bench(torch, lps, W, args, dev):
     log(f"cov: {per * 1e3:.2f} ms/call, {n * K / per:.3e} state.bin/s, {achieved:.2f} TFLOP/s FP64 "
         f"({achieved / PEAK_FP64_TFLOPS:.1%}); {valid}/{n} states valid")
     ctx.close()
+    valu = profiled_cov_valu()
+    issue = None if valu is None else valu * n * K / 64.0 / per / PEAK_FP64_WAVE_INSTR_PER_S
     return {"workload": name, "layout": COV_LAYOUT, "n_bins": K, "n_states": n, "splines_per_state": nb + 3,
             "correlation_in_between_knots": list(COV_CORR_INBETWEEN), "dtype": "f64",
             "value": n * K / per, "unit": UNIT, "ms_per_call": per * 1e3, "valid_states": valid,
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                          "flop_per_state_bin": COV_FLOP_PER_STATE_BIN, "state_bins_per_launch": n * K,
-                         "timed": "whole call (coefficients + evaluation + finalize), graph replays"}}
+                         "timed": "whole call (coefficients + evaluation + finalize), graph replays",
+                         "valu_lane_instr_per_state_bin": valu, "fp64_issue_frac": None if issue is None else round(issue, 4)}}
 
 
 def cpu_baseline_cov(name, n_states):

@@ -47,6 +47,7 @@
 #include <vector>
 
 #include "lps_internal.hpp"
+#include "lps_templates.hpp"
 #include "lps_spline.hpp"
 #include "lps_validate.hpp"
 

@@ -148,28 +148,6 @@ struct lps_ctx {
 
 namespace lps {
 
-// Per-bin templates at unit amplitudes: the A/E and T noise transfer of
-// Eq. (noise_tdi) (prefactor sin^2 xi sin^2 2xi, xi = 2 pi f L / c) times the
-// single-link OMS PSD per unit A_OMS^2 and TM PSD per unit A_TM^2 of Sec.
-// "Parametrized noise model", and the background factor 3 (H0/h)^2 / (4 pi^2 f^3)
-// of Eq. (Sh) per unit h^2 Omega (to be multiplied by the response R_c).
-__device__ inline void unit_templates(double fk, double L, double& oms_ae, double& oms_t, double& tm_ae,
-                                      double& tm_t, double& h) {
-  const double xi = 2.0 * kPi * fk * L / kClight;
-  const double sx = sin(xi), cx = cos(xi), s2x = sin(2.0 * xi);
-  const double pref = sx * sx * s2x * s2x;
-  const double r2 = 2.0e-3 / fk;
-  const double s_oms = (1.0 + r2 * r2 * r2 * r2) * (2.0 * kPi * fk / kClight) * (2.0 * kPi * fk / kClight);
-  const double r4 = 0.4e-3 / fk, r8 = fk / 8.0e-3;
-  const double q = 1.0 / (2.0 * kPi * fk * kClight);
-  const double s_tm = (1.0 + r4 * r4) * (1.0 + r8 * r8 * r8 * r8) * q * q;
-  oms_ae = 32.0 * pref * (2.0 + cx) * s_oms;
-  tm_ae = 32.0 * pref * 4.0 * (1.0 + cx + cx * cx) * s_tm;
-  oms_t = 64.0 * pref * (1.0 - cx) * s_oms;
-  tm_t = 64.0 * pref * 2.0 * (1.0 - cx) * (1.0 - cx) * s_tm;
-  h = 3.0 * kH0PerH * kH0PerH / (4.0 * kPi * kPi * fk * fk * fk);
-}
-
 // Launchers implemented in the .hip files.
 hipError_t build_tables(lps_ctx* ctx, hipStream_t s);
 // Maps a HIP result to a status; a failure is remembered (per host thread)

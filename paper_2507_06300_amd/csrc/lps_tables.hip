@@ -9,6 +9,7 @@
 #include <math.h>
 
 #include "lps_internal.hpp"
+#include "lps_templates.hpp"
 
 namespace lps {
 namespace {
