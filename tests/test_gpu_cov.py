@@ -202,3 +202,30 @@ def test_full_year_grid_sampled(lps):
             assert got[s] == want == -math.inf
         else:
             assert abs(got[s] - want) <= REL * abs(want), (s, got[s], want)
+
+
+def test_graph_replay(lps):
+    """The call captured into a HIP graph and replayed, with eager calls in
+    between, gives the eager result every time."""
+    name = "avg50_1000bins_64states"
+    ds, cds, P6, sb = _setup(name, 1000, "paper", 40, seed=9)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    full = ctx.loglike_batch(st)[0].clone()
+    out = torch.empty_like(full)
+    status = torch.empty(sb.n, dtype=torch.int32, device=full.device)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.loglike_batch(st, out=out, status=status)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.loglike_batch(st, out=out, status=status)
+    for rep in range(3):
+        out.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, full), rep
+        assert torch.equal(ctx.loglike_batch(st)[0], full)
