@@ -229,3 +229,36 @@ def test_graph_replay(lps):
         torch.cuda.synchronize()
         assert torch.equal(out, full), rep
         assert torch.equal(ctx.loglike_batch(st)[0], full)
+
+
+def test_eight_slots_and_routing_rules(lps):
+    """The maximum of eight spline slots (one routed nowhere), a full batch of
+    max_states, and the routing errors: a slot out of range, a slot used both
+    for a level and a correlation, a perturbed foreground."""
+    name = "avg50_1000bins_64states"
+    ds = W.make_dataset(name, n_bins=600, layout="paper")
+    x_lo, x_hi = W.band_edges(ds.f)
+    nb = ds.n_spl
+    sb = W.make_states(name, ds, n_states=12, seed_offset=11)
+    sb = W.append_splines(sb, np.random.default_rng(90), 4, (0, 6), x_lo, x_hi, 0.5)   # slots 4..7
+    cds = CV.CovDataset(base=ds, corr=(nb, nb + 2, nb + 3), n_spl=nb + 4)              # slot 5 unused
+    truth = W.append_splines(ds.truth, np.random.default_rng(91), 4, (1, 3), x_lo, x_hi, 0.5)
+    C, _, _ = CV.covariance(cds, truth.params[:, 0], _knots(truth, 0))
+    P6 = CV.unique_entries(W.complex_wishart_mean(np.random.default_rng(92), C, np.rint(ds.nk)).real)
+    ctx = lps.CovContext(ds.f, ds.nk, P6, ds.R, ds.route, cds.corr, cds.n_spl, max_states=sb.n,
+                         f_knee=ds.f_knee, arm_length=ds.arm_length)
+    got, status = ctx.loglike_batch(ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y))
+    got = got.cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    want = _oracle(cds, P6, sb, range(sb.n))
+    assert np.all(np.abs(got - want) <= REL * np.abs(want))
+    bad_routes = [((0, 1, 2), cds.n_spl), ((nb, nb + 1, cds.n_spl), cds.n_spl)]
+    for corr, n_spl in bad_routes:
+        with pytest.raises(lps.LpsError):
+            lps.CovContext(ds.f, ds.nk, P6, ds.R, ds.route, corr, n_spl, max_states=1)
+    fg_route = [list(r) for r in ds.route]
+    fg_route[3] = [0, 0, 0]
+    with pytest.raises(lps.LpsError):
+        lps.CovContext(ds.f, ds.nk, P6, ds.R, fg_route, cds.corr, cds.n_spl, max_states=1)
+    with pytest.raises(lps.LpsError):
+        lps.CovContext(ds.f, ds.nk, P6, ds.R, ds.route, cds.corr, 9, max_states=1)
