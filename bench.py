@@ -92,8 +92,8 @@ def parse():
     p.add_argument("--workload", default="year_912085bins_4096states")
     p.add_argument("--plain-states", type=int, default=64,
                    help="states timed on the plain FP64 per-state path (per-state cost is uniform)")
-    p.add_argument("--cpu-states", type=int, default=64, help="states in the CPU oracle sample")
-    p.add_argument("--cpu-cov-states", type=int, default=4, help="states in the full-covariance CPU sample")
+    p.add_argument("--cpu-states", type=int, default=128, help="states in the CPU oracle sample")
+    p.add_argument("--cpu-cov-states", type=int, default=32, help="states in the full-covariance CPU sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-grad", action="store_true")
@@ -151,8 +151,40 @@ def timed_graph(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) * 1e-3, g
 
 
-def cpu_baseline(name, n_states, dataset_bins=None):
-    """Time the FP64 oracle on a bounded sample of the workload (CPU leg)."""
+# Inputs of the CPU legs, set before the worker processes are forked.
+_CPU = {}
+
+
+def cpu_workers():
+    """Worker processes for the CPU legs: the cores this process may run on,
+    at most 16 (one GPU's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_map(fn, idx):
+    """fn over idx in worker processes forked from this one (called before the
+    process touches the GPU; the workers run numpy only)."""
+    import multiprocessing as mp
+    n = cpu_workers()
+    if n == 1:
+        return [fn(i) for i in idx], 1
+    with mp.get_context("fork").Pool(n) as pool:
+        return pool.map(fn, idx, chunksize=1), n
+
+
+def _cpu_diag_one(s):
+    from oracle import lps_oracle as O
+    ds, D, sb = _CPU["diag"]
+    return O.loglike(ds, D, sb.params[:, s], [sb.knots(s, j) for j in range(sb.n_spl)])
+
+
+def cpu_baseline(name, n_states):
+    """Time the FP64 oracle on a bounded sample of the workload (CPU leg), one
+    state per task over the host's cores."""
     from oracle import lps_oracle as O
     from synth import workloads as W
     ds = W.make_dataset(name)
@@ -160,15 +192,15 @@ def cpu_baseline(name, n_states, dataset_bins=None):
     S0, _, _ = O.psd(ds, ds.truth.params[:, 0], truth)
     D = S0 * ds.chi
     sb = W.make_states(name, ds)
+    _CPU["diag"] = (ds, D, sb)
     idx = list(range(min(n_states, sb.n)))
     t0 = time.perf_counter()
-    for s in idx:
-        O.loglike(ds, D, sb.params[:, s], [sb.knots(s, j) for j in range(sb.n_spl)])
+    _, cores = _cpu_map(_cpu_diag_one, idx)
     dt = time.perf_counter() - t0
     K = ds.f.size
-    return {"value": len(idx) * K / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+    return {"value": len(idx) * K / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": f"{len(idx)} of {sb.n} states x {K} bins x 3 channels of {name} "
-                      f"(numpy FP64, single thread), {dt:.1f} s"}
+                      f"(numpy FP64, one state per process, {cores} processes), {dt:.1f} s"}
 
 
 # Full-covariance leg: the one-year grid with the paper's layout (one noise
@@ -283,15 +315,21 @@ def cpu_baseline_cov(name, n_states):
     P6 = CV.unique_entries(W.complex_wishart_mean(np.random.default_rng(181), C, np.rint(ds.nk)).real)
     del C
     sb = _cov_states(W, ds, name, 182)
+    _CPU["cov"] = (cds, P6, sb)
     idx = list(range(min(n_states, sb.n)))
     t0 = time.perf_counter()
-    for s in idx:
-        CV.loglike(cds, P6, sb.params[:, s], [sb.knots(s, j) for j in range(sb.n_spl)])
+    _, cores = _cpu_map(_cpu_cov_one, idx)
     dt = time.perf_counter() - t0
     K = ds.f.size
-    return {"value": len(idx) * K / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+    return {"value": len(idx) * K / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": f"{len(idx)} of {sb.n} states x {K} bins (3x3 per bin) of {name}, {COV_LAYOUT} layout "
-                      f"+ 3 correlation splines (numpy FP64), {dt:.1f} s"}
+                      f"+ 3 correlation splines (numpy FP64, one state per process, {cores} processes), {dt:.1f} s"}
+
+
+def _cpu_cov_one(s):
+    from oracle import covariance as CV
+    cds, P6, sb = _CPU["cov"]
+    return CV.loglike(cds, P6, sb.params[:, s], [sb.knots(s, j) for j in range(sb.n_spl)])
 
 
 def main():
@@ -302,6 +340,17 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by walker; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    # CPU legs first: their worker processes are forked before this process
+    # initialises the GPU
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu oracle sample ({cpu_workers()} processes) ...")
+        cpu = cpu_baseline(args.workload, args.cpu_states)
+        log(f"  {cpu['value']:.3e} state.bin/s")
+        if not args.no_cov:
+            cpu["cov"] = cpu_baseline_cov(COV_WORKLOAD, args.cpu_cov_states)
+            log(f"  cov: {cpu['cov']['value']:.3e} state.bin/s")
+
     import torch
     import paper_2507_06300_amd as lps
     from synth import workloads as W
@@ -453,14 +502,9 @@ def main():
     if not args.no_cov:
         result["cov"] = cov_bench(torch, lps, W, args, dev)
 
-    # --- CPU oracle baseline ------------------------------------------------------
-    if not args.no_cpu:
-        log("cpu oracle sample ...")
-        result["cpu_baseline"] = cpu_baseline(name, args.cpu_states)
-        log(f"  {result['cpu_baseline']['value']:.3e} state.bin/s")
-        if not args.no_cov:
-            result["cpu_baseline"]["cov"] = cpu_baseline_cov(COV_WORKLOAD, args.cpu_cov_states)
-            log(f"  cov: {result['cpu_baseline']['cov']['value']:.3e} state.bin/s")
+    # --- CPU oracle baseline (timed before the GPU legs) ------------------------------
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
 
     print(json.dumps(result), flush=True)
 
@@ -551,6 +595,21 @@ def sampler_bench(torch, lps, W, args, dev):
     res["evidence"] = {"records": n_rec, "log_z": log_z, "sd_log_z": float(np.sqrt(var_z)),
                        "ms": e0.elapsed_time(e1)}
     sm.close()
+    # the two-step driver (templates only, then splines with the templates fixed)
+    from paper_2507_06300_amd.driver import two_step
+    tw = 32
+    init = np.ascontiguousarray(sb.params[:, :tw * n_temps])
+    burn, keep = 10, 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r2 = two_step(ctx, tw, betas, init, k_in_max, burn, keep, burn, keep, seed=7, step=0.05, precision="mixed")
+    torch.cuda.synchronize()
+    sec2 = time.perf_counter() - t0
+    r2.sampler.close()
+    res["two_step"] = {"walkers": tw, "temperatures": n_temps, "sweeps": 2 * (burn + keep), "seconds": sec2,
+                       "sweeps_per_s": 2 * (burn + keep) / sec2,
+                       "note": "eager sweeps with a host read of the cold chains after every kept step-1 sweep"}
+    log(f"two-step driver: {2 * (burn + keep)} sweeps of {tw * n_temps} chains in {sec2:.2f} s")
     ctx.close()
     return res
 
