@@ -333,21 +333,29 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
         }
       }
       // moments of the first piece: bins before the next breakpoint
+      auto accum_moments = [&](auto first_piece_only) {
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int pl = q * G + g;
-        const R lim1 = ((straddle >> pl) & 1ull) ? llim[wv][pl] : (R)INFINITY;
+        for (int g = 0; g < G; ++g) {
+          const int pl = q * G + g;
+          R lim1 = (R)INFINITY;
+          if constexpr (decltype(first_piece_only)::value)
+            lim1 = ((straddle >> pl) & 1ull) ? llim[wv][pl] : (R)INFINITY;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-          const R gq = xr[b] < lim1 ? gq_keep[g][b] : (R)0;
-          const R tt = T[g][b];
-          const R u1 = gq * tt, u2 = u1 * tt;
-          vf[4 + 4 * g + 0] += gq;
-          vf[4 + 4 * g + 1] += u1;
-          vf[4 + 4 * g + 2] += u2;
-          vf[4 + 4 * g + 3] += u2 * tt;
+          for (int b = 0; b < B; ++b) {
+            R gq = gq_keep[g][b];
+            if constexpr (decltype(first_piece_only)::value) gq = xr[b] < lim1 ? gq : (R)0;
+            const R tt = T[g][b];
+            const R u1 = gq * tt, u2 = u1 * tt;
+            vf[4 + 4 * g + 0] += gq;
+            vf[4 + 4 * g + 1] += u1;
+            vf[4 + 4 * g + 2] += u2;
+            vf[4 + 4 * g + 3] += u2 * tt;
+          }
         }
-      }
+      };
+      // a chunk inside one piece of every group needs no per-bin piece test
+      if (crossing) accum_moments(std::true_type{});
+      else accum_moments(std::false_type{});
       // the lane sums (B bins each) are added over the wave in the working
       // precision; the records themselves are double
       const R red = reduce_scatter<M>(vf, lred[wv], lane);
