@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include "lps_internal.hpp"
+#include "lps_math64.hpp"
 
 namespace lps {
 
@@ -19,9 +20,9 @@ struct Math<float> {
 
 template <>
 struct Math<double> {
-  __device__ static inline double exp2_(double v) { return exp2(v); }
-  __device__ static inline double log2_(double v) { return log2(v); }
-  __device__ static inline double rcp_(double v) { return 1.0 / v; }
+  __device__ static inline double exp2_(double v) { return exp2_d(v); }
+  __device__ static inline double log2_(double v) { return log2_d(v); }
+  __device__ static inline double rcp_(double v) { return rcp_d(v); }
 };
 
 template <int MODE>

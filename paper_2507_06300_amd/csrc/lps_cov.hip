@@ -47,6 +47,7 @@
 #include <vector>
 
 #include "lps_internal.hpp"
+#include "lps_math64.hpp"
 #include "lps_templates.hpp"
 #include "lps_spline.hpp"
 #include "lps_validate.hpp"
@@ -75,7 +76,6 @@ enum : int {
   kCovRows = 18
 };
 
-constexpr double kLog2e = 1.442695040888963407359924681001892137426645954153;
 
 // Per-slot values of one bin: 10^P_j for a slot feeding a diagonal term,
 // tanh P_j for a correlation slot; two fixed entries stand for "no spline".
@@ -212,48 +212,7 @@ __device__ inline StateScal state_scalars(const double* __restrict__ params, int
   return r;
 }
 
-// v_fma_f64 with every operand in a register.  (Written out because the
-// compiler otherwise turns a Horner step with a constant addend into a move
-// plus a two-address fmac.)
-__device__ inline double fma3(double a, double b, double c) {
-  double r;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
-
-// 2^y: y = n + f with n = rint(y), |f| <= 1/2; e^(f ln 2) by the Taylor series
-// to degree 13 (Horner), scaled by 2^n.  Propagates NaN; saturates to 0 / inf.
-__device__ inline double exp2_d(double y) {
-  const double n = rint(y);
-  const double t = (y - n) * kLn2;
-  double p = 1.0 / 6227020800.0;          // 1/13!
-  p = fma3(p, t, 1.0 / 479001600.0);      // 1/12!
-  p = fma3(p, t, 1.0 / 39916800.0);
-  p = fma3(p, t, 1.0 / 3628800.0);
-  p = fma3(p, t, 1.0 / 362880.0);
-  p = fma3(p, t, 1.0 / 40320.0);
-  p = fma3(p, t, 1.0 / 5040.0);
-  p = fma3(p, t, 1.0 / 720.0);
-  p = fma3(p, t, 1.0 / 120.0);
-  p = fma3(p, t, 1.0 / 24.0);
-  p = fma3(p, t, 1.0 / 6.0);
-  p = fma(p, t, 0.5);
-  p = fma(p, t, 1.0);
-  p = fma(p, t, 1.0);
-  const int e = (int)fmax(fmin(n, 2100.0), -2100.0);
-  return ldexp(p, e);
-}
-
 __device__ inline double exp10_d(double y) { return exp2_d(y * kLog2_10); }
-
-// 1/a for a normal positive a: hardware estimate, two Newton steps and a
-// residual correction (within an ulp or two).
-__device__ inline double rcp_d(double a) {
-  double q = __builtin_amdgcn_rcp(a);
-  q = fma(fma(-a, q, 1.0), q, q);
-  q = fma(fma(-a, q, 1.0), q, q);
-  return q;
-}
 
 // tanh q = sign(q) (1 - e) / (1 + e), e = exp(-2|q|) in (0, 1]
 __device__ inline double tanh_d(double q) {
@@ -262,52 +221,6 @@ __device__ inline double tanh_d(double q) {
   const double r = rcp_d(den);
   const double t = num * r;
   return copysign(fma(fma(-den, t, num), r, t), q);
-}
-
-// sqrt x for x >= 0 (0 for x = 0): hardware reciprocal square root estimate,
-// one coupled Newton step for sqrt and 1/(2 sqrt), and a residual correction.
-__device__ inline double sqrt_d(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  const double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  const double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  return x > 0.0 ? g : (x == 0.0 ? 0.0 : NAN);
-}
-
-// ln x for a positive normal x: x = m 2^e with m in [1/sqrt2, sqrt2),
-// ln m = 2 atanh s, s = (m - 1)/(m + 1), |s| < 0.172, by its odd series to
-// s^21 (truncation below 2^-56 relative); e ln 2 with a two-part ln 2 whose
-// leading part has trailing zero bits (exact products for |e| < 2^11).
-// Non-positive or non-finite x gives NaN (the caller flags the bin).
-__device__ inline double log_d(double x) {
-  int e = __builtin_amdgcn_frexp_exp(x);
-  double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
-  if (m < 0.70710678118654752440) {
-    m *= 2.0;
-    e -= 1;
-  }
-  const double num = m - 1.0, den = m + 1.0;
-  const double r = rcp_d(den);
-  double sv = num * r;
-  sv = fma(fma(-den, sv, num), r, sv);
-  const double z = sv * sv;
-  double p = 2.0 / 21.0;
-  p = fma3(p, z, 2.0 / 19.0);
-  p = fma3(p, z, 2.0 / 17.0);
-  p = fma3(p, z, 2.0 / 15.0);
-  p = fma3(p, z, 2.0 / 13.0);
-  p = fma3(p, z, 2.0 / 11.0);
-  p = fma3(p, z, 2.0 / 9.0);
-  p = fma3(p, z, 2.0 / 7.0);
-  p = fma3(p, z, 2.0 / 5.0);
-  p = fma3(p, z, 2.0 / 3.0);
-  const double lm = fma(sv * z, p, 2.0 * sv);
-  const double fe = (double)e;
-  const double res = fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, lm));
-  return x > 0.0 && x < INFINITY ? res : NAN;
 }
 
 struct CovPoint {
