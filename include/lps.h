@@ -424,6 +424,14 @@ int32_t lps_chunk_bins(lps_precision prec);
 lps_status lps_valu_probe(int device, double* fma_ns_per_wave_instr, double* trans_over_fma,
                           double* lane_instr_per_s);
 
+/*
+ * Diagnostic (not part of the hot path): applies one of the double-precision
+ * elementary functions of the batched FP64 kernels to x[0..n): fn = 0 exp2,
+ * 1 log2, 2 reciprocal, 3 square root, 4 natural logarithm; out[i] receives
+ * the result.  Device pointers, asynchronous on `stream`, no allocation.
+ */
+lps_status lps_math64_check(const double* x, int32_t n, int32_t fn, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

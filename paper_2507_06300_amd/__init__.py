@@ -72,7 +72,7 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10",
            "lps_stepping_stone", "lps_dic",
            "lps_data_periodogram", "lps_data_average", "lps_data_response",
-           "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build"]
+           "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build", "lps_math64_check"]
 
 _lib = None
 
@@ -127,10 +127,12 @@ def lib():
     L.lps_cov_destroy.argtypes = [vp]
     L.lps_cov_loglike_batch.argtypes = [vp, ctypes.POINTER(_States), vp, vp, vp]
     L.lps_cov_build.argtypes = [vp, ctypes.POINTER(_States), i32, i32, vp, vp, vp]
+    L.lps_math64_check.argtypes = [vp, i32, i32, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
                  "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response",
-                 "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build"]:
+                 "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build",
+                 "lps_math64_check"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -416,6 +418,18 @@ class CovContext:
         _check(lib().lps_cov_build(self._h, ctypes.byref(c), int(k0), int(k1), _ptr(C), _ptr(status),
                                    _stream(stream)), "lps_cov_build")
         return C, status
+
+
+MATH64 = {"exp2": 0, "log2": 1, "rcp": 2, "sqrt": 3, "log": 4}
+
+
+def math64_check(fn: str, x, stream=None):
+    """The library's FP64 elementary function `fn` (see MATH64) applied to x on the device."""
+    xd = _dev(x, torch.float64, torch.device("cuda"))
+    out = torch.empty_like(xd)
+    _check(lib().lps_math64_check(_ptr(xd), int(xd.numel()), MATH64[fn], _ptr(out), _stream(stream)),
+           "lps_math64_check")
+    return out
 
 
 def valu_probe(device=0):

@@ -1,10 +1,11 @@
 // Double-precision elementary functions of the batched kernels, written out
 // from their textbook constructions: a hardware estimate (v_rcp_f64,
 // v_rsq_f64) refined by Newton steps, range reduction plus a truncated Taylor
-// or atanh series.  Each is within an ulp or two of the correctly rounded
-// result on the arguments the kernels produce (positive normal numbers for
-// the reciprocal, square root and logarithm), at a fraction of the cost of
-// the library versions, which carry double-double steps.
+// or atanh series.  Each stays within a few ulp of the host C library over
+// the arguments the kernels produce (positive normal numbers for the
+// reciprocal, square root and logarithms; lps_math64_check exposes them for
+// that test), at a fraction of the cost of the library versions, which carry
+// double-double steps.
 #pragma once
 
 #include <math.h>

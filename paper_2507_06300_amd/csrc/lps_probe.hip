@@ -8,6 +8,7 @@
 // cost of a transcendental in FMA slots; the FMA time itself gives the
 // achieved lane-instruction rate of the device.
 #include "lps_internal.hpp"
+#include "lps_math64.hpp"
 
 namespace lps {
 namespace {
@@ -49,8 +50,32 @@ __global__ __launch_bounds__(256) void k_trans_chain(int iters, float seed, floa
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+__global__ void k_math64(int n, int fn, const double* __restrict__ x, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i];
+  double r;
+  switch (fn) {
+    case 0: r = exp2_d(v); break;
+    case 1: r = log2_d(v); break;
+    case 2: r = rcp_d(v); break;
+    case 3: r = sqrt_d(v); break;
+    default: r = log_d(v); break;
+  }
+  out[i] = r;
+}
+
 }  // namespace
 }  // namespace lps
+
+extern "C" lps_status lps_math64_check(const double* x, int32_t n, int32_t fn, double* out, void* stream) {
+  if (n == 0) return LPS_OK;
+  if (!x || !out) return LPS_E_NULL;
+  if (n < 0 || fn < 0 || fn > 4) return LPS_E_SHAPE;
+  hipLaunchKernelGGL(lps::k_math64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, fn, x,
+                     out);
+  return lps::device_status(hipGetLastError());
+}
 
 extern "C" lps_status lps_valu_probe(int device, double* fma_ns_per_wave_instr, double* trans_over_fma,
                                      double* lane_instr_per_s) {
