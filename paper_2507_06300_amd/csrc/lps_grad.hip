@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
                                               int ref_chunk, const R* __restrict__ tab,
                                               const double* __restrict__ x64, const double* __restrict__ bx,
                                               const R* __restrict__ coef, const int32_t* __restrict__ n_int,
-                                              const StateScalars* __restrict__ scal, double* __restrict__ rec,
+                                              const StateScalars* __restrict__ scal, R* __restrict__ rec,
                                               int2* __restrict__ gidx, double* __restrict__ glast,
                                               double* __restrict__ moments) {
   constexpr int G = Groups<MODE>::G;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
       const int s = sub + q;
       const size_t ro = (size_t)s * n_chunks + chunk;
       if ((invalid >> (q * G)) & 1ull) {   // invalid state: the finisher reports it
-        if (lane < NV) rec[ro * NV + lane] = 0.0;
+        if (lane < NV) rec[ro * NV + lane] = (R)0;
         if (lane < G) gidx[ro * G + lane] = make_int2(0, 0);
         continue;
       }
@@ -357,9 +357,9 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
       if (crossing) accum_moments(std::true_type{});
       else accum_moments(std::false_type{});
       // the lane sums (B bins each) are added over the wave in the working
-      // precision; the records themselves are double
+      // precision and stored in it (the finisher adds the records in double)
       const R red = reduce_scatter<M>(vf, lred[wv], lane);
-      if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = (double)red;
+      if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = red;
       {
         int a0 = 0, a1 = 0;
 #pragma unroll
@@ -439,8 +439,9 @@ __device__ inline uint64_t wave_or64(uint64_t v) {
 // written to `moments` by k_grad.  Lanes walk 64 chunks at a time; a
 // segmented scan keyed by the starting piece sums the chunks of one piece,
 // so the order of every sum is fixed.
+template <typename RT>
 __device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks, int ni,
-                             const double* __restrict__ rec, const int2* __restrict__ gidx,
+                             const RT* __restrict__ rec, const int2* __restrict__ gidx,
                              const double* __restrict__ glast, const double* __restrict__ moments,
                              double (*mo)[4]) {
   for (int p = 0; p < 4; ++p) mo[lane][p] = 0.0;
@@ -453,7 +454,7 @@ __device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks
     const int2 ab = have ? gidx[ro * G + g] : make_int2(-1, -1);
     double v[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) v[p] = have ? rec[ro * NV + 4 + 4 * g + p] : 0.0;
+    for (int p = 0; p < 4; ++p) v[p] = have ? (double)rec[ro * NV + 4 + 4 * g + p] : 0.0;
     if (ab.y > ab.x) {
       const double* last = glast + (ro * G + g) * 4;
 #pragma unroll
@@ -617,13 +618,15 @@ __device__ void spline_backward_wave(int lane, const double* __restrict__ x, con
   wave_lds_sync();
 }
 
-// One wave per state: stitches the chunk records into per-piece moments,
-// then forms logL, the template-parameter gradients and the knot gradients.
+// One wave per state: stitches the chunk records (type RT: the working
+// precision of the adjoint kernel) into per-piece moments, then forms logL,
+// the template-parameter gradients and the knot gradients.
+template <typename RT>
 __global__ __launch_bounds__(256) void k_grad_finish(
     int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay, double x_knee,
     const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
     const double* __restrict__ kx, const double* __restrict__ ky, const int32_t* __restrict__ n_int,
-    const double* __restrict__ bx, const double* __restrict__ rec, const int2* __restrict__ gidx,
+    const double* __restrict__ bx, const RT* __restrict__ rec, const int2* __restrict__ gidx,
     const double* __restrict__ glast, const double* __restrict__ moments, const double* __restrict__ c0,
     const uint32_t* __restrict__ status_ws, double* __restrict__ logL, double* __restrict__ dparams,
     double* __restrict__ dkx, double* __restrict__ dky, uint32_t* __restrict__ status) {
@@ -638,9 +641,9 @@ __global__ __launch_bounds__(256) void k_grad_finish(
   double sums[4] = {0.0, 0.0, 0.0, 0.0};
   if (st == 0) {
     for (int c = lane; c < n_chunks; c += kWave) {
-      const double* r = rec + ((size_t)s * n_chunks + c) * NV;
+      const RT* r = rec + ((size_t)s * n_chunks + c) * NV;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sums[i] += r[i];
+      for (int i = 0; i < 4; ++i) sums[i] += (double)r[i];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) sums[i] = wave_sum(sums[i]);
@@ -716,7 +719,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(
 
 template <typename R, int B>
 hipError_t dispatch_grad(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, const R* tab, const R* coef,
-                         int NV, double* rec, int2* gidx, double* glast, hipStream_t s) {
+                         int NV, R* rec, int2* gidx, double* glast, hipStream_t s) {
   const Layout& L = ctx->lay;
   const int items = n_chunks * n_tiles;
   dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
@@ -766,8 +769,11 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
   const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
   const int G = ctx->lay.n_grp;
   const int NV = grad_nv(ctx->lay);
-  double* rec = ctx->gpartial;
-  int2* gidx = (int2*)(rec + (size_t)n * n_chunks * NV);
+  // records in the working precision, then piece indices and last-piece
+  // moments (the layout is sized for double records, so it always fits)
+  const size_t rec_bytes = (size_t)n * n_chunks * NV * (mixed ? sizeof(float) : sizeof(double));
+  char* base = (char*)ctx->gpartial;
+  int2* gidx = (int2*)(base + ((rec_bytes + 15) & ~(size_t)15));
   double* glast = (double*)(gidx + (size_t)n * n_chunks * G);
   long target = 8192;
   long tile = ((long)n * n_chunks) / target;
@@ -776,18 +782,28 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
   if (tile > n) tile = n;
   const int n_tiles = (n + (int)tile - 1) / (int)tile;
   timing_begin(ctx, s);
-  if (mixed)
+  const dim3 fgrid((n + kWavesPerBlock - 1) / kWavesPerBlock), fblock(kWave * kWavesPerBlock);
+  if (mixed) {
+    float* rec = (float*)base;
     e = dispatch_grad<float, kBGrad32>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab32, ctx->coef32, NV, rec, gidx,
                                        glast, s);
-  else
+    if (e != hipSuccess) return e;
+    timing_end(ctx, s);
+    hipLaunchKernelGGL(k_grad_finish<float>, fgrid, fblock, 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
+                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
+                       ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams,
+                       dkx, dky, status);
+  } else {
+    double* rec = (double*)base;
     e = dispatch_grad<double, kBGrad64>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab64, ctx->coef64, NV, rec,
                                         gidx, glast, s);
-  if (e != hipSuccess) return e;
-  timing_end(ctx, s);
-  hipLaunchKernelGGL(k_grad_finish, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kWave * kWavesPerBlock), 0,
-                     s, n, ctx->n_spl, ctx->n_params, NV, n_chunks, ctx->lay, log10(ctx->f_knee), st->params,
-                     st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->n_int, ctx->bx, rec, gidx, glast,
-                     ctx->moments, ctx->c0, ctx->status_ws, logL, dparams, dkx, dky, status);
+    if (e != hipSuccess) return e;
+    timing_end(ctx, s);
+    hipLaunchKernelGGL(k_grad_finish<double>, fgrid, fblock, 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
+                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
+                       ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams,
+                       dkx, dky, status);
+  }
   return hipGetLastError();
 }
 
