@@ -18,9 +18,10 @@
 //                 first-piece moments per group in one 16/32-value record,
 //                 last-piece moments and interior pieces for chunks that
 //                 straddle a knot;
-//   k_grad_finish one wave per state: stitches the chunk records into
-//                 per-piece moments (fixed order, deterministic), then logL,
-//                 template gradients and the Akima backward, lane per knot.
+//   k_grad_finish one workgroup per state: stitches the chunk records into
+//                 per-piece moments (one group per wave, fixed order,
+//                 deterministic), then logL, template gradients and the
+//                 Akima backward (one spline per wave, lane per knot).
 #include <math.h>
 
 #include <type_traits>
@@ -416,11 +417,18 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
 }
 
 // Per-wave LDS of the finishing kernel.
-struct FinishLds {
-  double mo[kMaxGroups][kMaxKnots][4];   // per-piece moments M^p_i of every group
+// Per-wave LDS of the spline backward.
+struct BackLds {
   double m[kMaxKnots], h[kMaxKnots], s[kMaxKnots], w[kMaxKnots];
   double sbn[kMaxKnots], sb[kMaxKnots], pl[kMaxKnots], pr[kMaxKnots], cr[kMaxKnots], cl[kMaxKnots];
   double wbs[kMaxKnots], q[kMaxKnots], hb[kMaxKnots];
+};
+
+// LDS of the finishing kernel: one workgroup per state.
+struct FinishLds {
+  double mo[kMaxGroups][kMaxKnots][4];   // per-piece moments M^p_i of every group
+  double part[kWavesPerBlock][4];        // per-wave partial record sums
+  BackLds back[kWavesPerBlock];
 };
 
 __device__ inline uint64_t wave_or64(uint64_t v) {
@@ -499,7 +507,7 @@ __device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks
 // sequential adjoint becomes a gather of fixed neighbours through LDS.
 __device__ void spline_backward_wave(int lane, const double* __restrict__ x, const double* __restrict__ y, int n,
                                      const double (&M)[4], double* __restrict__ dy, double* __restrict__ dx,
-                                     FinishLds& L) {
+                                     BackLds& L) {
   const int i = lane;
   const bool knot = i < n, seg = i + 1 < n;
   const double xi = knot ? x[i] : 0.0;
@@ -618,9 +626,11 @@ __device__ void spline_backward_wave(int lane, const double* __restrict__ x, con
   wave_lds_sync();
 }
 
-// One wave per state: stitches the chunk records (type RT: the working
-// precision of the adjoint kernel) into per-piece moments, then forms logL,
-// the template-parameter gradients and the knot gradients.
+// One workgroup per state: the four waves add the chunk records' logL and
+// template sums (a quarter of the chunks each, combined in wave order), stitch
+// the groups' records (type RT: the working precision of the adjoint kernel)
+// into per-piece moments one group per wave, then form the template-parameter
+// gradients and run the spline backward one spline per wave.
 template <typename RT>
 __global__ __launch_bounds__(256) void k_grad_finish(
     int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay, double x_knee,
@@ -630,33 +640,40 @@ __global__ __launch_bounds__(256) void k_grad_finish(
     const double* __restrict__ glast, const double* __restrict__ moments, const double* __restrict__ c0,
     const uint32_t* __restrict__ status_ws, double* __restrict__ logL, double* __restrict__ dparams,
     double* __restrict__ dkx, double* __restrict__ dky, uint32_t* __restrict__ status) {
-  __shared__ FinishLds lds[kWavesPerBlock];
+  __shared__ FinishLds L;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = uniform(threadIdx.x >> 6);
-  const int s = uniform(blockIdx.x * kWavesPerBlock + wv);
-  if (s >= n_states) return;
-  FinishLds& L = lds[wv];
+  const int s = blockIdx.x;
+  if (s >= n_states) return;   // the whole workgroup
   const int G = lay.n_grp;
   uint32_t st = status_ws[s];
   double sums[4] = {0.0, 0.0, 0.0, 0.0};
-  if (st == 0) {
-    for (int c = lane; c < n_chunks; c += kWave) {
+  if (st == 0) {   // uniform over the workgroup
+    double ps[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = wv * kWave + lane; c < n_chunks; c += kWavesPerBlock * kWave) {
       const RT* r = rec + ((size_t)s * n_chunks + c) * NV;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sums[i] += (double)r[i];
+      for (int i = 0; i < 4; ++i) ps[i] += (double)r[i];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sums[i] = wave_sum(sums[i]);
+    for (int i = 0; i < 4; ++i) ps[i] = wave_sum(ps[i]);
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) L.part[wv][i] = ps[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      for (int w = 0; w < kWavesPerBlock; ++w) sums[i] += L.part[w][i];
   }
   const double Lv = c0[0] - sums[0];
   if (st == 0 && !isfinite(Lv)) st |= LPS_ST_PSD;
-  if (lane == 0) {
+  if (wv == 0 && lane == 0) {
     if (status) status[s] = st;
     logL[s] = st ? -INFINITY : Lv;
   }
   if (st) {
-    if (lane < n_params) dparams[lane * (size_t)n_states + s] = 0.0;
-    for (int j = 0; j < n_spl; ++j) {
+    if (wv == 0 && lane < n_params) dparams[lane * (size_t)n_states + s] = 0.0;
+    for (int j = wv; j < n_spl; j += kWavesPerBlock) {
       int a, cn;
       knot_range(off, kcnt, s * n_spl + j, a, cn);
       if (a < 0) continue;
@@ -667,41 +684,44 @@ __global__ __launch_bounds__(256) void k_grad_finish(
     }
     return;
   }
-  for (int g = 0; g < G; ++g)
+  for (int g = wv; g < G; g += kWavesPerBlock)
     stitch_group(lane, s, g, G, NV, n_chunks, n_int[s * G + g], rec, gidx, glast, moments, L.mo[g]);
-  const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
-  const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
-  double r_oms = sums[1], r_tm = sums[2];
-  double du = 0.0, dalpha = 0.0;
-  for (int g = 0; g < G; ++g) {
-    const int ni = n_int[s * G + g];
-    double m0 = 0.0, m1x = 0.0;
-    if (lane < ni) {
-      const double b = bx[(size_t)(s * G + g) * kMaxKnots + lane];
-      m0 = L.mo[g][lane][0];
-      m1x = L.mo[g][lane][1] + (b - x_knee) * m0;
+  __syncthreads();
+  if (wv == 0) {
+    const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
+    const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
+    double r_oms = sums[1], r_tm = sums[2];
+    double du = 0.0, dalpha = 0.0;
+    for (int g = 0; g < G; ++g) {
+      const int ni = n_int[s * G + g];
+      double m0 = 0.0, m1x = 0.0;
+      if (lane < ni) {
+        const double b = bx[(size_t)(s * G + g) * kMaxKnots + lane];
+        m0 = L.mo[g][lane][0];
+        m1x = L.mo[g][lane][1] + (b - x_knee) * m0;
+      }
+      m0 = wave_sum(m0);
+      m1x = wave_sum(m1x);
+      switch (lay.grp_kind[g]) {
+        case kGOms: r_oms = m0; break;
+        case kGTm: r_tm = m0; break;
+        case kGSgwb:
+          du = kLn10 * m0;
+          dalpha = kLn10 * m1x;
+          break;
+        default: break;
+      }
     }
-    m0 = wave_sum(m0);
-    m1x = wave_sum(m1x);
-    switch (lay.grp_kind[g]) {
-      case kGOms: r_oms = m0; break;
-      case kGTm: r_tm = m0; break;
-      case kGSgwb:
-        du = kLn10 * m0;
-        dalpha = kLn10 * m1x;
-        break;
-      default: break;
+    if (lane == 0) {
+      dparams[LPS_P_AOMS * (size_t)n_states + s] = 2.0 * r_oms / a_oms;
+      dparams[LPS_P_ATM * (size_t)n_states + s] = 2.0 * r_tm / a_tm;
+      dparams[LPS_P_U * (size_t)n_states + s] = du;
+      dparams[LPS_P_ALPHA * (size_t)n_states + s] = dalpha;
+      if (n_params > 4) dparams[LPS_P_UFG * (size_t)n_states + s] = kLn10 * sums[3];
     }
-  }
-  if (lane == 0) {
-    dparams[LPS_P_AOMS * (size_t)n_states + s] = 2.0 * r_oms / a_oms;
-    dparams[LPS_P_ATM * (size_t)n_states + s] = 2.0 * r_tm / a_tm;
-    dparams[LPS_P_U * (size_t)n_states + s] = du;
-    dparams[LPS_P_ALPHA * (size_t)n_states + s] = dalpha;
-    if (n_params > 4) dparams[LPS_P_UFG * (size_t)n_states + s] = kLn10 * sums[3];
   }
   // spline knots: the moments of every group fed by the spline, summed in group order
-  for (int j = 0; j < n_spl; ++j) {
+  for (int j = wv; j < n_spl; j += kWavesPerBlock) {
     int a, n;
     knot_range(off, kcnt, s * n_spl + j, a, n);
     if (n == 0) continue;
@@ -713,7 +733,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(
         for (int p = 0; p < 4; ++p) M[p] += kLn10 * L.mo[g][lane][p];
       }
     }
-    spline_backward_wave(lane, kx + a, ky + a, n, M, dky + a, dkx + a, L);
+    spline_backward_wave(lane, kx + a, ky + a, n, M, dky + a, dkx + a, L.back[wv]);
   }
 }
 
@@ -782,7 +802,7 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
   if (tile > n) tile = n;
   const int n_tiles = (n + (int)tile - 1) / (int)tile;
   timing_begin(ctx, s);
-  const dim3 fgrid((n + kWavesPerBlock - 1) / kWavesPerBlock), fblock(kWave * kWavesPerBlock);
+  const dim3 fgrid(n), fblock(kWave * kWavesPerBlock);   // one workgroup per state
   if (mixed) {
     float* rec = (float*)base;
     e = dispatch_grad<float, kBGrad32>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab32, ctx->coef32, NV, rec, gidx,
