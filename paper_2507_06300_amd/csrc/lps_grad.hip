@@ -100,12 +100,12 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
   // same work order as the forward kernel: tile groups per chunk over
   // XCD-contiguous block ranges
   const int item = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
-  const int tg = item / (n_chunks * kTileGroup);
-  const int rem = item - tg * (n_chunks * kTileGroup);
-  const int tl = min(kTileGroup, n_tiles - tg * kTileGroup);
+  const int tg = item / (n_chunks * kTileGroupGrad);
+  const int rem = item - tg * (n_chunks * kTileGroupGrad);
+  const int tl = min(kTileGroupGrad, n_tiles - tg * kTileGroupGrad);
   if (tl <= 0) return;
   const int chunk = rem / tl;
-  const int t = tg * kTileGroup + (rem - chunk * tl);
+  const int t = tg * kTileGroupGrad + (rem - chunk * tl);
   if (chunk >= n_chunks) return;
   const int s_begin = t * tile;
   const int s_end = min(s_begin + tile, n_states);

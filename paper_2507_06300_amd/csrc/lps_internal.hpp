@@ -196,7 +196,8 @@ __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v);
 // by workgroup index.  xcd_block renumbers the grid so that each XCD works
 // through one contiguous range of logical blocks; a bijection on [0, n).
 constexpr int kXcds = 8;
-constexpr int kTileGroup = 4;   // state tiles that share a chunk's table rows in L2
+constexpr int kTileGroup = 8;       // forward: state tiles that share a chunk's table rows in L2
+constexpr int kTileGroupGrad = 4;   // adjoint (its records per state tile fill L2 sooner)
 __device__ inline int xcd_block(int b, int n) {
   const int q = n / kXcds, r = n % kXcds;
   const int x = b % kXcds, local = b / kXcds;
