@@ -39,6 +39,8 @@ with its reasons in the design notes) fixes one:
   validity     the state checks of the diagonal model, and C_k positive
                definite at every bin (Sylvester's criterion on the correlation
                form of C_k); otherwise logL = -inf and the PSD status bit.
+  gradient     loglike_grad(): the matrix-calculus derivative written out in
+               forward mode (see its docstring), pinned by finite differences.
 """
 from __future__ import annotations
 
@@ -143,14 +145,115 @@ def state_status(cds, params, knots, k_max=64):
     return st
 
 
-def loglike(cds, P6, params, knots, k_max=64):
-    """- sum_k N_k (tr(C_k^-1 P_k) + ln det C_k); -inf for an invalid state."""
-    if state_status(cds, params, knots, k_max):
-        return -math.inf
+def loglike_terms(cds, P6, params, knots):
+    """Per-bin terms N_k (tr(C_k^-1 P_k) + ln det C_k), [K], of a valid state."""
     C, _, _ = covariance(cds, params, knots)
     P = data_matrix(P6)
     X = np.linalg.solve(C, P)                     # C^-1 P per bin
     tr = X[:, 0, 0] + X[:, 1, 1] + X[:, 2, 2]
     sign, logdet = np.linalg.slogdet(C)
     assert np.all(sign > 0)
-    return -math.fsum((cds.nk * (tr + logdet)).tolist())
+    return cds.nk * (tr + logdet)
+
+
+def loglike(cds, P6, params, knots, k_max=64):
+    """- sum_k N_k (tr(C_k^-1 P_k) + ln det C_k); -inf for an invalid state."""
+    if state_status(cds, params, knots, k_max):
+        return -math.inf
+    return -math.fsum(loglike_terms(cds, P6, params, knots).tolist())
+
+
+def _covariance_tangent(sn, dsn, dsh, q, dq):
+    """dC [K][3][3] from tangents of Sn, Sh [3][K] and of Q_0..Q_2 [3][K],
+    by forward differentiation of the construction of covariance()."""
+    r01, r02, r12 = vine_correlations(q[0], q[1], q[2])
+    p12 = np.tanh(q[2])
+    dr01 = (1.0 - r01 * r01) * dq[0]
+    dr02 = (1.0 - r02 * r02) * dq[1]
+    dp12 = (1.0 - p12 * p12) * dq[2]
+    S = np.sqrt((1.0 - r01 * r01) * (1.0 - r02 * r02))
+    # S = 0 only where a correlation is exactly +-1: S is then 0 for every
+    # value of the other one, and its tangent is 0
+    num = r01 * dr01 * (1.0 - r02 * r02) + r02 * dr02 * (1.0 - r01 * r01)
+    dS = np.where(S > 0.0, -num / np.where(S > 0.0, S, 1.0), 0.0)
+    dr12 = dr01 * r02 + r01 * dr02 + dp12 * S + p12 * dS
+    r = {(0, 1): (r01, dr01), (0, 2): (r02, dr02), (1, 2): (r12, dr12)}
+    K = sn.shape[1]
+    dC = np.zeros((K, 3, 3))
+    for c in range(3):
+        dC[:, c, c] = dsn[c] + dsh[c]
+    for (a, b), (rv, drv) in r.items():
+        hs = np.sqrt(sn[a] * sn[b])
+        dhs = (dsn[a] * sn[b] + sn[a] * dsn[b]) / (2.0 * hs)
+        dC[:, a, b] = dC[:, b, a] = drv * hs + rv * dhs
+    return dC
+
+
+def loglike_grad(cds, P6, params, knots, k_max=64):
+    """(logL, dlogL/dparams, [dlogL/dy per spline], [dlogL/dx per spline]).
+
+    Along a change dC of the covariance, tr(C^-1 P) + ln det C changes by
+    tr(G dC) with G = C^-1 - C^-1 P C^-1 (matrix calculus: d C^-1 =
+    -C^-1 dC C^-1, d ln det C = tr(C^-1 dC)), so
+        dlogL/dtheta = - sum_k N_k tr(G_k dC_k/dtheta).
+    dC/dtheta by forward differentiation of covariance(): the template
+    parameters act on Sn and Sh as in the diagonal model, a spline value
+    P_j(x_k) through every term routed to it (factor ln 10 10^P_j) or through
+    its correlation Q_i; knots through the spline tangents of App. A.
+    Edge abscissae get 0.  Invalid states give (-inf, zeros)."""
+    npar = len(params)
+    zy = [np.zeros(len(kx)) for (kx, _) in knots]
+    zx = [np.zeros(len(kx)) for (kx, _) in knots]
+    if state_status(cds, params, knots, k_max):
+        return -math.inf, np.zeros(npar), zy, zx
+    logL = loglike(cds, P6, params, knots, k_max)
+    pt = O.perturbed_terms(cds, params, knots)
+    sn = pt[O.TERM_OMS] + pt[O.TERM_TM]
+    q = correlation_splines(cds, knots)
+    C, _, _ = covariance(cds, params, knots)
+    Ci = np.linalg.inv(C)
+    G = Ci - Ci @ data_matrix(P6) @ Ci
+    nu = cds.nk
+    K = nu.size
+    z3 = np.zeros((3, K))
+
+    def per_bin(dsn, dsh, dq):
+        dC = _covariance_tangent(sn, dsn, dsh, q, dq)
+        return -nu * np.einsum("kab,kba->k", G, dC)
+
+    lnf = np.log(cds.f / cds.f_knee)[None, :]
+    dp = np.zeros(npar)
+    dp[0] = math.fsum(per_bin(2.0 * pt[O.TERM_OMS] / params[0], z3, z3).tolist())
+    dp[1] = math.fsum(per_bin(2.0 * pt[O.TERM_TM] / params[1], z3, z3).tolist())
+    dp[2] = math.fsum(per_bin(z3, O.LN10 * pt[O.TERM_SGWB], z3).tolist())
+    dp[3] = math.fsum(per_bin(z3, lnf * pt[O.TERM_SGWB], z3).tolist())
+    if npar > 4:
+        dp[4] = math.fsum(per_bin(z3, O.LN10 * pt[O.TERM_FG], z3).tolist())
+    x = np.log10(cds.f)
+    dys, dxs = [], []
+    for j, (kx, ky) in enumerate(knots):
+        n = len(kx)
+        if n == 0:
+            dys.append(np.zeros(0))
+            dxs.append(np.zeros(0))
+            continue
+        # dlogL/dP_j(x_k): every diagonal term routed to slot j, and the
+        # correlation spline(s) it carries
+        dsn, dsh, dq = np.zeros((3, K)), np.zeros((3, K)), np.zeros((3, K))
+        for tau in range(4):
+            for c in range(3):
+                if cds.route[tau][c] == j:
+                    tgt = dsn if tau in (O.TERM_OMS, O.TERM_TM) else dsh
+                    tgt[c] += O.LN10 * pt[tau, c]
+        for i in range(3):
+            if cds.corr[i] == j:
+                dq[i] = 1.0
+        gbar = per_bin(dsn, dsh, dq)
+        _, J = O.spline_tangents(kx, ky, x)
+        tot = np.array([math.fsum(gbar * J[:, m]) for m in range(J.shape[1])])
+        dy = tot[:n].copy()
+        dx = np.zeros(n)
+        dx[1:n - 1] = tot[n:]
+        dys.append(dy)
+        dxs.append(dx)
+    return logL, dp, dys, dxs

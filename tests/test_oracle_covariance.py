@@ -34,8 +34,9 @@ def _states(ds, n, seed, corr_inbetween=(0, 4), height_sd=0.5):
     return W.append_splines(sb, np.random.default_rng(100 + seed), 3, corr_inbetween, x_lo, x_hi, height_sd)
 
 
-def _cds(ds, corr=(4, 5, 6)):
-    return CV.CovDataset(base=ds, corr=corr, n_spl=ds.n_spl + 3)
+def _cds(ds, corr=None):
+    nb = ds.n_spl
+    return CV.CovDataset(base=ds, corr=corr if corr is not None else (nb, nb + 1, nb + 2), n_spl=nb + 3)
 
 
 def _random_data(ds, rng):
@@ -219,3 +220,134 @@ def test_single_draw_wishart_mean():
     assert np.all(np.linalg.matrix_rank(Pc) == 1)
     s = np.sqrt(np.einsum("kaa,kbb->kab", C, C))
     assert np.all(np.abs(acc / reps - C) < 6.0 * s / math.sqrt(reps))
+
+
+# --------------------------------------------------------------------------
+# gradient
+# --------------------------------------------------------------------------
+
+def _fd(cds, P6, p, kn, move, h):
+    """Central difference of logL, summed bin by bin (the large common part of
+    the per-bin terms cancels before the sum)."""
+    pa, ka = move(+h)
+    pb, kb = move(-h)
+    ta = CV.loglike_terms(cds, P6, pa, ka)
+    tb = CV.loglike_terms(cds, P6, pb, kb)
+    return -math.fsum((ta - tb).tolist()) / (2.0 * h)
+
+
+def _grad_fd_errors(cds, P6, p, kn):
+    """Largest |analytic - finite difference| / (family scale) over the template
+    parameters, knot heights and interior knot positions."""
+    _, dp, dys, dxs = CV.loglike_grad(cds, P6, p, kn)
+    worst = {}
+
+    def upd(fam, got, want, scale):
+        worst[fam] = max(worst.get(fam, 0.0), abs(got - want) / scale)
+
+    sp = np.abs(dp * np.where(np.arange(p.size) < 2, p, 1.0)).max() + 1.0
+    for i in range(p.size):
+        h = 1e-6 * abs(p[i]) if i < 2 else 1e-6
+
+        def mv(d, i=i):
+            q = p.copy()
+            q[i] += d
+            return q, kn
+        fd = _fd(cds, P6, p, kn, mv, h)
+        u = p[i] if i < 2 else 1.0
+        upd("params", dp[i] * u, fd * u, sp)
+    sy = max(np.abs(g).max() for g in dys if g.size) + 1.0
+    sx = max(np.abs(g).max() for g in dxs if g.size) + 1.0
+    for j, (kx, ky) in enumerate(kn):
+        for i in range(kx.size):
+            def my(d, j=j, i=i):
+                k2 = list(kn)
+                y2 = ky.copy()
+                y2[i] += d
+                k2[j] = (kx, y2)
+                return p, k2
+            upd("heights", dys[j][i], _fd(cds, P6, p, kn, my, 1e-6), sy)
+            if 0 < i < kx.size - 1:
+                def mx(d, j=j, i=i):
+                    k2 = list(kn)
+                    x2 = kx.copy()
+                    x2[i] += d
+                    k2[j] = (x2, ky)
+                    return p, k2
+                # step scaled to the narrower neighbouring interval, where the
+                # spline's third derivative grows as width^-2
+                hx = 1e-5 * min(kx[i] - kx[i - 1], kx[i + 1] - kx[i])
+                upd("positions", dxs[j][i], _fd(cds, P6, p, kn, mx, hx), sx)
+            else:
+                assert dxs[j][i] == 0.0
+    return worst
+
+
+@pytest.mark.parametrize("layout", ["paper", "split_fg"])
+def test_gradient_matches_finite_differences(layout):
+    """Every template parameter, knot height and interior knot position of
+    all seven splines (four diagonal, three correlation) against central
+    differences of the likelihood itself."""
+    ds = W.make_dataset(NAME, n_bins=160, layout=layout)
+    cds = _cds(ds)
+    rng = np.random.default_rng(20)
+    P6 = _random_data(ds, rng)
+    sb = _states(ds, 2, 21, corr_inbetween=(1, 3))
+    for s in range(sb.n):
+        worst = _grad_fd_errors(cds, P6, sb.params[:, s], _knots(sb, s))
+        assert set(worst) == {"params", "heights", "positions"}
+        for fam, e in worst.items():
+            assert e < 1e-6, (layout, s, fam, e)
+
+
+def test_gradient_zero_correlation_is_the_diagonal_gradient():
+    """Correlation slots routed nowhere: the diagonal oracle's gradient for the
+    diagonal splines, exact zeros for the unrouted ones."""
+    ds = _base(250)
+    rng = np.random.default_rng(22)
+    P6 = _random_data(ds, rng)
+    sb = _states(ds, 3, 23)
+    cds = _cds(ds, corr=(-1, -1, -1))
+    for s in range(sb.n):
+        kn = _knots(sb, s)
+        l1, dp1, dy1, dx1 = CV.loglike_grad(cds, P6, sb.params[:, s], kn)
+        l0, dp0, dy0, dx0 = O.loglike_grad(ds, P6[:3], sb.params[:, s], kn[:4])
+        assert abs(l1 - l0) <= 1e-13 * abs(l0)
+        u = np.where(np.arange(dp0.size) < 2, sb.params[:dp0.size, s], 1.0)
+        np.testing.assert_allclose(dp1 * u, dp0 * u, rtol=1e-9, atol=1e-9 * np.abs(dp0 * u).max())
+        for j in range(4):
+            np.testing.assert_allclose(dy1[j], dy0[j], rtol=1e-9, atol=1e-9 * (np.abs(dy0[j]).max() + 1.0))
+            np.testing.assert_allclose(dx1[j], dx0[j], rtol=1e-9, atol=1e-9 * (np.abs(dx0[j]).max() + 1.0))
+        for j in range(4, 7):
+            assert np.all(dy1[j] == 0.0) and np.all(dx1[j] == 0.0)
+
+
+def test_gradient_vanishes_at_the_model():
+    """P = C makes the likelihood stationary (the Wishart term's maximum): the
+    whole gradient is rounding-sized next to its value at other data."""
+    ds = _base(250)
+    cds = _cds(ds)
+    sb = _states(ds, 1, 24, corr_inbetween=(1, 3))
+    p, kn = sb.params[:, 0], _knots(sb, 0)
+    C, _, _ = CV.covariance(cds, p, kn)
+    _, dp0, dy0, dx0 = CV.loglike_grad(cds, CV.unique_entries(C), p, kn)
+    _, dp1, dy1, dx1 = CV.loglike_grad(cds, _random_data(ds, np.random.default_rng(25)), p, kn)
+    u = np.where(np.arange(dp0.size) < 2, p[:dp0.size], 1.0)
+    assert np.abs(dp0 * u).max() <= 1e-9 * np.abs(dp1 * u).max()
+    big_y = max(np.abs(g).max() for g in dy1)
+    big_x = max(np.abs(g).max() for g in dx1)
+    assert max(np.abs(g).max() for g in dy0) <= 1e-9 * big_y
+    assert max(np.abs(g).max() for g in dx0) <= 1e-9 * big_x
+
+
+def test_gradient_of_an_invalid_state_is_zero():
+    ds = _base(100)
+    cds = _cds(ds)
+    sb = _states(ds, 1, 26)
+    p, kn = sb.params[:, 0], _knots(sb, 0)
+    bad = list(kn)
+    kx, ky = kn[5]
+    bad[5] = (kx[::-1].copy(), ky)
+    l, dp, dy, dx = CV.loglike_grad(cds, _random_data(ds, np.random.default_rng(27)), p, bad)
+    assert l == -math.inf and np.all(dp == 0.0)
+    assert all(np.all(g == 0.0) for g in dy + dx)

@@ -202,3 +202,48 @@ def test_mutation_cov_data_transposed_half(monkeypatch):
         return M            # lower triangle left empty
     monkeypatch.setattr(CV, "data_matrix", dm)
     assert _cov_pins_fail()
+
+
+def _cov_grad_pins_fail():
+    bodies = [lambda: cpins.test_gradient_matches_finite_differences("paper"),
+              cpins.test_gradient_vanishes_at_the_model]
+    return any(_fails(b) for b in bodies)
+
+
+def _tangent_with(mistake):
+    """A copy of the covariance tangent with one planted mistake."""
+    def tangent(sn, dsn, dsh, q, dq):
+        r01, r02, r12 = CV.vine_correlations(q[0], q[1], q[2])
+        p12 = np.tanh(q[2])
+        dr01 = (1.0 - r01 * r01) * dq[0]
+        dr02 = (1.0 - r02 * r02) * dq[1]
+        dp12 = dq[2] if mistake == "no_tanh_factor" else (1.0 - p12 * p12) * dq[2]
+        S = np.sqrt((1.0 - r01 * r01) * (1.0 - r02 * r02))
+        dS = -(r01 * dr01 * (1.0 - r02 * r02) + r02 * dr02 * (1.0 - r01 * r01)) / S
+        if mistake == "no_dS":
+            dS = 0.0 * dS
+        dr12 = dr01 * r02 + r01 * dr02 + dp12 * S + p12 * dS
+        K = sn.shape[1]
+        dC = np.zeros((K, 3, 3))
+        for c in range(3):
+            dC[:, c, c] = dsn[c] + dsh[c]
+        for (a, b), (rv, drv) in {(0, 1): (r01, dr01), (0, 2): (r02, dr02), (1, 2): (r12, dr12)}.items():
+            hs = np.sqrt(sn[a] * sn[b])
+            bb = a if mistake == "half_index" else b
+            dhs = (dsn[a] * sn[bb] + sn[a] * dsn[b]) / (2.0 * hs)
+            dC[:, a, b] = dC[:, b, a] = drv * hs + rv * dhs
+        return dC
+    return tangent
+
+
+@pytest.mark.parametrize("mistake", ["no_dS", "no_tanh_factor", "half_index"])
+def test_mutation_cov_gradient(monkeypatch, mistake):
+    monkeypatch.setattr(CV, "_covariance_tangent", _tangent_with(mistake))
+    assert _cov_grad_pins_fail()
+
+
+def test_mutation_cov_gradient_copy_is_faithful(monkeypatch):
+    """The mutation copy without a mistake passes the pins (so a failure above
+    comes from the planted mistake alone)."""
+    monkeypatch.setattr(CV, "_covariance_tangent", _tangent_with(None))
+    assert not _cov_grad_pins_fail()
