@@ -393,6 +393,17 @@ lps_status lps_cov_destroy(lps_cov_ctx* ctx);
 lps_status lps_cov_loglike_batch(lps_cov_ctx* ctx, const lps_states* st /*[host]*/, double* logL,
                                  uint32_t* status, void* stream);
 
+/* logL and its gradient for every state of the batch (hand-written adjoint,
+ * FP64): dparams[p][s] = dlogL/dparams[p][s] (same layout as params) and
+ * dknot_x, dknot_y = dlogL/d knot_x, knot_y (the states' CSR layout; edge
+ * abscissae get 0), with the conventions of lps_loglike_grad_batch.  Invalid
+ * states, including those whose covariance is not positive definite, get
+ * logL = -inf and zero derivatives.  One wave per state walks every bin;
+ * asynchronous on `stream`, no allocation; one batch at a time per context. */
+lps_status lps_cov_loglike_grad_batch(lps_cov_ctx* ctx, const lps_states* st /*[host]*/, double* logL,
+                                      double* dparams, double* dknot_x, double* dknot_y, uint32_t* status,
+                                      void* stream);
+
 /* The model covariance for bins [k0, k1) of every state: C[s][e][k - k0] with
  * e = AA, EE, TT, AE, AT, ET.  Structurally invalid states get NaN rows and
  * their status bits (the positive-definiteness bit is left to

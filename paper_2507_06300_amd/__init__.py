@@ -72,7 +72,8 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10",
            "lps_stepping_stone", "lps_dic",
            "lps_data_periodogram", "lps_data_average", "lps_data_response",
-           "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build", "lps_math64_check"]
+           "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch", "lps_cov_build",
+           "lps_math64_check"]
 
 _lib = None
 
@@ -126,13 +127,14 @@ def lib():
     L.lps_cov_create.argtypes = [ctypes.POINTER(_CovDesc), ctypes.c_int, ctypes.POINTER(vp)]
     L.lps_cov_destroy.argtypes = [vp]
     L.lps_cov_loglike_batch.argtypes = [vp, ctypes.POINTER(_States), vp, vp, vp]
+    L.lps_cov_loglike_grad_batch.argtypes = [vp, ctypes.POINTER(_States), vp, vp, vp, vp, vp, vp]
     L.lps_cov_build.argtypes = [vp, ctypes.POINTER(_States), i32, i32, vp, vp, vp]
     L.lps_math64_check.argtypes = [vp, i32, i32, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
                  "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response",
-                 "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_build",
-                 "lps_math64_check"]:
+                 "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch",
+                 "lps_cov_build", "lps_math64_check"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -363,6 +365,7 @@ class CovContext:
         self.Rfg = None if Rfg is None else _dev(Rfg, torch.float64, dev)
         self.n_bins = int(self.f.numel())
         self.n_spl = int(n_spl)
+        self.n_params = 4 if Rfg is None else 5
         self.max_states = int(max_states)
         d = _CovDesc()
         d.n_bins = self.n_bins
@@ -407,6 +410,21 @@ class CovContext:
         _check(lib().lps_cov_loglike_batch(self._h, ctypes.byref(c), _ptr(logL), _ptr(status), _stream(stream)),
                "lps_cov_loglike_batch")
         return logL, status
+
+    def loglike_grad_batch(self, st: States, stream=None):
+        """logL, dlogL/dparams [n_params][n], dlogL/dknot_x, dlogL/dknot_y (the
+        states' CSR layout) and status."""
+        n = st.n
+        logL = torch.empty(n, dtype=torch.float64, device=self.device)
+        dparams = torch.empty((self.n_params, n), dtype=torch.float64, device=self.device)
+        dkx = torch.empty_like(st.knot_x)
+        dky = torch.empty_like(st.knot_y)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = st._c()
+        _check(lib().lps_cov_loglike_grad_batch(self._h, ctypes.byref(c), _ptr(logL), _ptr(dparams), _ptr(dkx),
+                                                _ptr(dky), _ptr(status), _stream(stream)),
+               "lps_cov_loglike_grad_batch")
+        return logL, dparams, dkx, dky, status
 
     def build(self, st: States, k0=0, k1=None, stream=None):
         """Model covariance rows C[s][6][k1 - k0] (AA, EE, TT, AE, AT, ET) and status."""
