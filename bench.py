@@ -224,7 +224,8 @@ PEAK_FP64_TFLOPS = 78.6
 # FP64 VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 FP64 instruction per
 # SIMD every 4 cycles.
 PEAK_FP64_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
-COV_SOURCES = ["paper_2507_06300_amd/csrc/lps_cov.hip", "paper_2507_06300_amd/csrc/lps_templates.hpp",
+COV_SOURCES = ["paper_2507_06300_amd/csrc/lps_cov.hip", "paper_2507_06300_amd/csrc/lps_cov_common.hpp",
+               "paper_2507_06300_amd/csrc/lps_templates.hpp",
                "paper_2507_06300_amd/csrc/lps_math64.hpp"]
 COV_PROFILE = "profiles/k_cov_eval_year_912085bins_4096states.md"
 
@@ -290,10 +291,16 @@ def cov_bench(torch, lps, W, args, dev):
     achieved = n * K * COV_FLOP_PER_STATE_BIN / per / 1e12
     log(f"cov: {per * 1e3:.2f} ms/call, {n * K / per:.3e} state.bin/s, {achieved:.2f} TFLOP/s FP64 "
         f"({achieved / PEAK_FP64_TFLOPS:.1%}); {valid}/{n} states valid")
+    # the adjoint (logL and every parameter and knot derivative) of the same batch
+    tg, _ = timed_graph(torch, lambda: ctx.loglike_grad_batch(st), steps, 1)
+    per_g = tg / steps
+    log(f"cov adjoint: {per_g * 1e3:.2f} ms/call, {n * K / per_g:.3e} state.bin/s")
     ctx.close()
     valu = profiled_cov_valu()
     issue = None if valu is None else valu * n * K / 64.0 / per / PEAK_FP64_WAVE_INSTR_PER_S
     return {"workload": name, "layout": COV_LAYOUT, "n_bins": K, "n_states": n, "splines_per_state": nb + 3,
+            "grad": {"ms_per_call": per_g * 1e3, "state_bin_grad_evals_per_s": n * K / per_g,
+                     "timed": "whole call (coefficients + adjoint + spline backward), graph replays"},
             "correlation_in_between_knots": list(COV_CORR_INBETWEEN), "dtype": "f64",
             "value": n * K / per, "unit": UNIT, "ms_per_call": per * 1e3, "valid_states": valid,
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblps.so")
 SOURCES = ["lps_api.hip", "lps_tables.hip", "lps_coeffs.hip", "lps_forward.hip", "lps_psd.hip",
            "lps_plain.hip", "lps_grad.hip", "lps_probe.hip", "lps_sampler.hip", "lps_evidence.hip", "lps_data.hip",
-           "lps_cov.hip"]
+           "lps_cov.hip", "lps_cov_grad.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -50,76 +50,14 @@
 #include "lps_math64.hpp"
 #include "lps_templates.hpp"
 #include "lps_spline.hpp"
-#include "lps_spline_back.hpp"
 #include "lps_validate.hpp"
+#include "lps_cov_common.hpp"
+
 
 namespace lps {
 namespace {
 
-constexpr int kCovMaxSpl = LPS_COV_MAX_SPLINES;
-constexpr int kCovB = 2;                    // bins per lane in one chunk
-constexpr int kCovChunk = kWave * kCovB;    // 128 bins
-constexpr int kCovMaxTile = 8;              // states per wave
-constexpr int kCovGroups = 64;              // chunk groups per dataset (fixed by K alone)
-
-// Rows of the per-bin table [kCovRows][k_pad]; every PSD-valued row is
-// divided by sigma_k.
-enum : int {
-  kRx = 0,       // log10 f
-  kRnu = 1,      // N_k (0 for padding)
-  kRomsAE = 2,   // OMS transfer x single-link PSD per unit A_OMS^2, channels A and E
-  kRomsT = 3,    //   channel T
-  kRtmAE = 4,    // TM, per unit A_TM^2
-  kRtmT = 5,
-  kRsg = 6,      // R_c 3 (H0/h)^2 / (4 pi^2 f^3), c = A, E, T
-  kRP = 9,       // data rows AA, EE, TT, AE, AT, ET
-  kRfg = 15,     // foreground shape, c = A, E, T (0 without a foreground)
-  kCovRows = 18
-};
-
-
-// Per-slot values of one bin: 10^P_j for a slot feeding a diagonal term,
-// tanh P_j for a correlation slot; two fixed entries stand for "no spline".
-constexpr int kSlotOne = kCovMaxSpl;        // 1 (an unperturbed diagonal term)
-constexpr int kSlotZero = kCovMaxSpl + 1;   // 0 (zero correlation)
-constexpr int kSlots = kCovMaxSpl + 2;
-
-struct CovRoute {
-  uint8_t g[3][3];      // [OMS, TM, SGWB][channel] slot of the factor 10^P (kSlotOne: none)
-  uint8_t gc[3];        // slots of tanh Q0, tanh Q1, tanh Q2 (kSlotZero: none)
-  uint32_t diag_mask;   // bit j: slot j feeds a diagonal term (value 10^P_j)
-  uint32_t corr_mask;   // bit j: slot j is a correlation term (value tanh P_j)
-  int32_t sg_slot;      // slot carrying the background in all channels and nothing else, or -1
-};
-
-}  // namespace
-}  // namespace lps
-
-struct lps_cov_ctx {
-  int device;
-  int32_t n_bins, k_pad, n_chunks, chunks_per_group, n_groups;
-  int32_t n_spl, n_params, k_max, max_states, has_fg;
-  lps::CovRoute rt;
-  double x_knee, x_first, x_last;
-  double* tab;          // [kCovRows][k_pad]
-  double* bx;           // [max_states][kCovMaxSpl][kMaxKnots] piece start abscissae
-  double* coef;         // [max_states][kCovMaxSpl][kMaxKnots][4]
-  int32_t* npc;         // [max_states][kCovMaxSpl] pieces (0: disabled or invalid state)
-  uint32_t* status;     // [max_states]
-  double* partial;      // [max_states][n_groups]
-  double* sigma;        // [K] reference level sigma_k of the scaled table
-  double* c0;           // [1] 3 sum_k N_k ln sigma_k
-};
-
-namespace lps {
-namespace {
-
-__device__ inline double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
+using namespace covk;
 
 __global__ void k_cov_table(int K, int k_pad, const double* __restrict__ f, const double* __restrict__ nk,
                             const double* __restrict__ P, const double* __restrict__ R,
@@ -197,134 +135,6 @@ __global__ __launch_bounds__(256) void k_cov_coeffs(int n_states, int n_spl, int
   }
 }
 
-struct StateScal {
-  double w_oms, w_tm, u, alpha, efg;
-};
-
-__device__ inline StateScal state_scalars(const double* __restrict__ params, int n_states, int s, int has_fg) {
-  StateScal r;
-  const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
-  const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
-  r.w_oms = a_oms * a_oms;
-  r.w_tm = a_tm * a_tm;
-  r.u = params[LPS_P_U * (size_t)n_states + s];
-  r.alpha = params[LPS_P_ALPHA * (size_t)n_states + s];
-  r.efg = has_fg ? exp10(params[LPS_P_UFG * (size_t)n_states + s]) : 0.0;
-  return r;
-}
-
-__device__ inline double exp10_d(double y) { return exp2_d(y * kLog2_10); }
-
-// tanh q = sign(q) (1 - e) / (1 + e), e = exp(-2|q|) in (0, 1]
-__device__ inline double tanh_d(double q) {
-  const double e = exp2_d(-2.0 * kLog2e * fabs(q));
-  const double den = 1.0 + e, num = 1.0 - e;
-  const double r = rcp_d(den);
-  const double t = num * r;
-  return copysign(fma(fma(-den, t, num), r, t), q);
-}
-
-struct CovPoint {
-  double d[3];    // C_cc (scaled)
-  double sn[3];   // Sn_c (scaled)
-  double r01, r02, r12;
-};
-
-// The value of slot j at one bin: 10^P, tanh P, or P itself for an unused slot.
-// lin = u + alpha (x - log10 f_knee) is added to the exponent of the slot that
-// carries the background in every channel (rt.sg_slot), which then holds the
-// whole background factor 10^(u + alpha (x - x_knee) + P).
-__device__ inline double slot_value(double pv, int j, const CovRoute& rt, double lin) {
-  if (j == rt.sg_slot) return exp10_d(pv + lin);
-  if ((rt.diag_mask >> j) & 1u) return exp10_d(pv);
-  if ((rt.corr_mask >> j) & 1u) return tanh_d(pv);
-  return pv;
-}
-
-// The model at one bin from the slot values V (read through `val(slot)`) and
-// the bin's table entries (read through `row(r)`).
-template <typename Val, typename Row>
-__device__ inline void cov_point(const Val& val, const CovRoute& rt, const StateScal& sc, double x_knee, const Row& row,
-                                 CovPoint& o) {
-  const double hf = rt.sg_slot >= 0 ? 1.0 : exp10_d(sc.u + sc.alpha * (row(kRx) - x_knee));
-  const double oms[3] = {row(kRomsAE), row(kRomsAE), row(kRomsT)};
-  const double tm[3] = {row(kRtmAE), row(kRtmAE), row(kRtmT)};
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double sn = sc.w_oms * oms[c] * val(rt.g[0][c]) + sc.w_tm * tm[c] * val(rt.g[1][c]);
-    const double sh = row(kRsg + c) * hf * val(rt.g[2][c]) + row(kRfg + c) * sc.efg;
-    o.d[c] = sn + sh;
-    o.sn[c] = sn;
-  }
-  o.r01 = val(rt.gc[0]);
-  o.r02 = val(rt.gc[1]);
-  o.r12 = o.r01 * o.r02 + val(rt.gc[2]) * sqrt_d((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
-}
-
-// N_k (tr(C^-1 P) + ln det C) at one bin in scaled units; `bad` is set where
-// C is not positive definite or the term is not finite.
-template <typename Row>
-__device__ inline double cov_term(const CovPoint& p, const Row& row, bool& bad) {
-  const double d0 = p.d[0], d1 = p.d[1], d2 = p.d[2];
-  const double n0 = p.sn[0], n1 = p.sn[1], n2 = p.sn[2];
-  const double q01 = p.r01 * p.r01 * (n0 * n1);
-  const double q02 = p.r02 * p.r02 * (n0 * n2);
-  const double q12 = p.r12 * p.r12 * (n1 * n2);
-  const double a00 = d1 * d2 - q12, a11 = d0 * d2 - q02, a22 = d0 * d1 - q01;
-  const double det = d0 * a00 - d1 * q02 - d2 * q01 + 2.0 * (p.r01 * p.r02 * p.r12) * (n0 * n1 * n2);
-  const double a01 = sqrt_d(n0 * n1) * (p.r02 * p.r12 * n2 - p.r01 * d2);
-  const double a02 = sqrt_d(n0 * n2) * (p.r01 * p.r12 * n1 - p.r02 * d1);
-  const double a12 = sqrt_d(n1 * n2) * (p.r01 * p.r02 * n0 - p.r12 * d0);
-  const double num = a00 * row(kRP + 0) + a11 * row(kRP + 1) + a22 * row(kRP + 2) +
-                     2.0 * (a01 * row(kRP + 3) + a02 * row(kRP + 4) + a12 * row(kRP + 5));
-  const double tr = num / det;
-  const double ld = log_d(det);
-  const bool ok = d0 > 0.0 && a22 > 0.0 && det > 0.0 && isfinite(tr) && isfinite(ld);
-  bad = bad || !ok;
-  return row(kRnu) * (tr + ld);
-}
-
-struct CovArgs {
-  const double* tab;
-  int k_pad, n_chunks, chunks_per_group, n_groups;
-  int n_states, tile, n_tiles, n_spl, has_fg;
-  CovRoute rt;
-  double x_knee;
-  const double* params;
-  uint32_t* status;
-  const double* bx;
-  const double* coef;
-  const int32_t* npc;
-  double* partial;
-};
-
-struct LdsVal {
-  const double* p;   // &lval[wave][0][lane]
-  __device__ double operator()(int j) const { return p[j * kWave]; }
-};
-
-struct TabRow {
-  const double* __restrict__ p;
-  size_t stride;
-  __device__ double operator()(int r) const { return p[r * stride]; }
-};
-
-// The piece of spline (s, j) that holds a bin and the start of the next one.
-struct PieceRec {
-  double x0, a0, a1, a2, a3, xn;
-};
-
-__device__ inline PieceRec load_piece(const CovArgs& A, size_t row, int q, int np) {
-  PieceRec p;
-  p.x0 = A.bx[row + q];
-  const double* c = A.coef + (row + q) * 4;
-  p.a0 = c[0];
-  p.a1 = c[1];
-  p.a2 = c[2];
-  p.a3 = c[3];
-  p.xn = q + 1 < np ? A.bx[row + q + 1] : INFINITY;
-  return p;
-}
 
 // Four waves per SIMD: the register budget of 128 costs a few spills to
 // scratch but hides more latency than three waves without them.
@@ -509,318 +319,10 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
     out[(size_t)(3 + e) * n_out] = sqrt_d(p.sn[pa[e]]) * r[e] * sqrt_d(p.sn[pb[e]]) * sg;
 }
 
-// ---------------------------------------------------------------------------
-// Adjoint of the full-covariance likelihood (FP64), one wave per state.
-//
-// Per bin, with G = C^-1 - C^-1 P C^-1 (the derivative of tr(C^-1 P) + ln det C
-// with respect to the symmetric C), dlogL/dC_aa = -N G_aa and, for the pair
-// a < b, dlogL/dC_ab = -2 N G_ab.  Through C_cc = Sn_c + Sh_c and
-// C_ab = r_ab sqrt(Sn_a Sn_b):
-//   dSh_c = dC_cc,   dSn_c = dC_cc + sum_{b != c} dC_cb C_cb / (2 Sn_c),
-//   dr_ab = dC_ab sqrt(Sn_a Sn_b),
-// then the vine (r_ET = r_AE r_AT + p S, S = sqrt((1 - r_AE^2)(1 - r_AT^2))),
-// dq = dr (1 - r^2) for r = tanh q, and d(10^P)/dP = ln 10 10^P for the level
-// slots.  The slot derivatives dlogL/dP_j(x) are summed per spline piece as
-// moments M_m = sum dP t^m (t from the piece start), and the Akima backward
-// turns them into knot derivatives.  A lane keeps the moments of the piece
-// under the cursor in registers; a chunk that crosses a knot adds the bins
-// beyond it piece by piece (wave sums) and the finished piece's moments go to
-// the wave's moment table in LDS.
-// ---------------------------------------------------------------------------
-struct CovGradLds {
-  double val[kSlots][kWave];         // slot values of the current bin
-  double gp[kSlots][kWave];          // dlogL / d(slot argument) of the current bin
-  double t[kCovMaxSpl][kWave];       // x - start of the bin's piece
-  int pc[kCovMaxSpl][kWave];         // the bin's piece
-  PieceRec rec[kCovMaxSpl];
-  int cur[kCovMaxSpl][3];            // cursor piece, last piece of this chunk, pieces
-  double mo[kCovMaxSpl][kMaxKnots][4];   // moments of every finished piece
-};
-static_assert(sizeof(BackLds) <= 2 * kSlots * kWave * sizeof(double), "backward LDS aliases val and gp");
 
-__device__ inline void mo_add(double* __restrict__ m, const double (&v)[4]) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) m[i] += v[i];
-}
+}  // namespace
 
-__global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
-                                                  const double* __restrict__ kx, const double* __restrict__ ky,
-                                                  int n_params, const double* __restrict__ c0,
-                                                  double* __restrict__ logL, double* __restrict__ dparams,
-                                                  double* __restrict__ dkx, double* __restrict__ dky,
-                                                  uint32_t* __restrict__ status_out) {
-  __shared__ CovGradLds lds[4];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = (int)(threadIdx.x / kWave);
-  const int s = uniform(blockIdx.x * 4 + w);
-  if (s >= A.n_states) return;
-  CovGradLds& L = lds[w];
-  const size_t kp = (size_t)A.k_pad;
-  const int n_spl = A.n_spl;
-  uint32_t st = A.status[s];
-  auto zero_outputs = [&]() {
-    if (lane < n_params) dparams[lane * (size_t)A.n_states + s] = 0.0;
-    for (int j = 0; j < n_spl; ++j) {
-      int a, cn;
-      knot_range(off, kcnt, s * n_spl + j, a, cn);
-      if (a < 0) continue;
-      for (int i = lane; i < cn; i += kWave) {
-        dkx[a + i] = 0.0;
-        dky[a + i] = 0.0;
-      }
-    }
-  };
-  if (st != 0u) {
-    if (lane == 0) {
-      logL[s] = -INFINITY;
-      if (status_out) status_out[s] = st;
-    }
-    zero_outputs();
-    return;
-  }
-  double* mo = &L.mo[0][0][0];
-  for (int i = lane; i < kCovMaxSpl * kMaxKnots * 4; i += kWave) mo[i] = 0.0;
-  // cursors at the first bin
-  const double x_first = A.tab[kRx * kp];
-#pragma unroll 1
-  for (int j = 0; j < n_spl; ++j) {
-    const int np = A.npc[(size_t)s * kCovMaxSpl + j];
-    int cur = -1;
-    if (np > 0) {
-      const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-      const double bl = lane < np ? A.bx[row + lane] : INFINITY;
-      cur = uniform(max(__popcll(__ballot(bl <= x_first)) - 1, 0));
-      const PieceRec pr = load_piece(A, row, cur, np);
-      if (lane == 0) L.rec[j] = pr;
-    }
-    if (lane == 0) {
-      L.cur[j][0] = cur;
-      L.cur[j][1] = cur;
-      L.cur[j][2] = np;
-    }
-  }
-  L.val[kSlotOne][lane] = 1.0;
-  L.val[kSlotZero][lane] = 0.0;
-  wave_lds_sync();
-  const LdsVal val{&L.val[0][lane]};
-  const StateScal sc = state_scalars(A.params, A.n_states, s, A.has_fg);
-  double acc[kCovMaxSpl][4];
-#pragma unroll
-  for (int j = 0; j < kCovMaxSpl; ++j)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc[j][m] = 0.0;
-  double lsum = 0.0, g_wo = 0.0, g_wt = 0.0, g_lin = 0.0, g_linx = 0.0, g_fg = 0.0;
-  bool bad = false;
-  for (int ch = 0; ch < A.n_chunks; ++ch) {
-    const int kb = ch * kCovChunk;
-    const double* tb = A.tab + kb + lane;
-    const double xl = A.tab[kRx * kp + kb + kCovChunk - 1];
-    // pieces that start inside this chunk
-#pragma unroll 1
-    for (int j = 0; j < n_spl; ++j) {
-      const int cur = uniform(L.cur[j][0]);
-      if (cur < 0 || !(xl >= L.rec[j].xn)) continue;
-      const int np = uniform(L.cur[j][2]);
-      const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-      int hi = cur + 1;
-      while (hi + 1 < np && A.bx[row + hi + 1] <= xl) ++hi;
-      if (lane == 0) L.cur[j][1] = hi;
-    }
-    wave_lds_sync();
-#pragma unroll 1
-    for (int b = 0; b < kCovB; ++b) {
-      const TabRow row{tb + b * kWave, kp};
-      const double x = row(kRx);
-      const double lin = sc.u + sc.alpha * (x - A.x_knee);
-      // forward: slot values, the bin's piece and abscissa offset per spline
-#pragma unroll 1
-      for (int j = 0; j < n_spl; ++j) {
-        const int cur = uniform(L.cur[j][0]);
-        double pv = 0.0, tt = 0.0;
-        int pc = cur;
-        if (cur >= 0) {
-          PieceRec pr = L.rec[j];
-          const int hi = uniform(L.cur[j][1]);
-          if (hi != cur) {
-            const size_t rw = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-            const int np = uniform(L.cur[j][2]);
-            for (int q = cur + 1; q <= hi; ++q) {
-              const PieceRec nq = load_piece(A, rw, q, np);
-              if (x >= nq.x0) {
-                pr = nq;
-                pc = q;
-              }
-            }
-          }
-          tt = x - pr.x0;
-          pv = pr.a0 + tt * (pr.a1 + tt * (pr.a2 + tt * pr.a3));
-        }
-        L.val[j][lane] = slot_value(pv, j, A.rt, lin);
-        L.t[j][lane] = tt;
-        L.pc[j][lane] = pc;
-        L.gp[j][lane] = 0.0;
-      }
-      wave_lds_sync();
-      CovPoint p;
-      cov_point(val, A.rt, sc, A.x_knee, row, p);
-      lsum += cov_term(p, row, bad);
-      // adjoint of the bin
-      const double nu = row(kRnu);
-      const double d0 = p.d[0], d1 = p.d[1], d2 = p.d[2];
-      const double n0 = p.sn[0], n1 = p.sn[1], n2 = p.sn[2];
-      const double s01 = sqrt_d(n0 * n1), s02 = sqrt_d(n0 * n2), s12 = sqrt_d(n1 * n2);
-      const double c01 = p.r01 * s01, c02 = p.r02 * s02, c12 = p.r12 * s12;
-      const double a00 = d1 * d2 - c12 * c12, a11 = d0 * d2 - c02 * c02, a22 = d0 * d1 - c01 * c01;
-      const double a01 = c02 * c12 - c01 * d2, a02 = c01 * c12 - c02 * d1, a12 = c01 * c02 - c12 * d0;
-      const double det = d0 * a00 + c01 * a01 + c02 * a02;
-      const double id = rcp_d(det);
-      const double ci[3][3] = {{a00 * id, a01 * id, a02 * id}, {a01 * id, a11 * id, a12 * id},
-                               {a02 * id, a12 * id, a22 * id}};
-      const double P[3][3] = {{row(kRP + 0), row(kRP + 3), row(kRP + 4)},
-                              {row(kRP + 3), row(kRP + 1), row(kRP + 5)},
-                              {row(kRP + 4), row(kRP + 5), row(kRP + 2)}};
-      double X[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) X[a][c] = ci[a][0] * P[0][c] + ci[a][1] * P[1][c] + ci[a][2] * P[2][c];
-      auto Gm = [&](int a, int c) { return ci[a][c] - (X[a][0] * ci[0][c] + X[a][1] * ci[1][c] + X[a][2] * ci[2][c]); };
-      // dlogL / dC (pairs counted once)
-      const double gC00 = -nu * Gm(0, 0), gC11 = -nu * Gm(1, 1), gC22 = -nu * Gm(2, 2);
-      const double gC01 = -2.0 * nu * Gm(0, 1), gC02 = -2.0 * nu * Gm(0, 2), gC12 = -2.0 * nu * Gm(1, 2);
-      const double gsh[3] = {gC00, gC11, gC22};
-      const double gsn[3] = {gC00 + (gC01 * c01 + gC02 * c02) / (2.0 * n0),
-                             gC11 + (gC01 * c01 + gC12 * c12) / (2.0 * n1),
-                             gC22 + (gC02 * c02 + gC12 * c12) / (2.0 * n2)};
-      double gr01 = gC01 * s01, gr02 = gC02 * s02;
-      const double gr12 = gC12 * s12;
-      const double pp = val(A.rt.gc[2]);
-      const double S = sqrt_d((1.0 - p.r01 * p.r01) * (1.0 - p.r02 * p.r02));
-      double gpp = gr12 * S;
-      if (S > 0.0) {
-        gr01 += gr12 * (p.r02 - pp * p.r01 * (1.0 - p.r02 * p.r02) / S);
-        gr02 += gr12 * (p.r01 - pp * p.r02 * (1.0 - p.r01 * p.r01) / S);
-      } else {
-        gr01 += gr12 * p.r02;
-        gr02 += gr12 * p.r01;
-      }
-      const double gq[3] = {gr01 * (1.0 - p.r01 * p.r01), gr02 * (1.0 - p.r02 * p.r02), gpp * (1.0 - pp * pp)};
-      // slot derivatives (a slot may serve several terms: accumulate in LDS)
-      const double oms[3] = {row(kRomsAE), row(kRomsAE), row(kRomsT)};
-      const double tm[3] = {row(kRtmAE), row(kRtmAE), row(kRtmT)};
-      const double hf = A.rt.sg_slot >= 0 ? 1.0 : exp10_d(lin);
-      double gl = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double fo = val(A.rt.g[0][c]), ft = val(A.rt.g[1][c]), fh = val(A.rt.g[2][c]);
-        const double to = sc.w_oms * oms[c] * fo, tt2 = sc.w_tm * tm[c] * ft, th = row(kRsg + c) * hf * fh;
-        g_wo += gsn[c] * oms[c] * fo;
-        g_wt += gsn[c] * tm[c] * ft;
-        g_fg += gsh[c] * row(kRfg + c) * sc.efg;
-        gl += gsh[c] * th;
-        if (A.rt.g[0][c] < kCovMaxSpl) L.gp[A.rt.g[0][c]][lane] += kLn10 * gsn[c] * to;
-        if (A.rt.g[1][c] < kCovMaxSpl) L.gp[A.rt.g[1][c]][lane] += kLn10 * gsn[c] * tt2;
-        if (A.rt.g[2][c] < kCovMaxSpl) L.gp[A.rt.g[2][c]][lane] += kLn10 * gsh[c] * th;
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        if (A.rt.gc[i] < kCovMaxSpl) L.gp[A.rt.gc[i]][lane] += gq[i];
-      g_lin += kLn10 * gl;
-      g_linx += kLn10 * gl * (x - A.x_knee);
-      wave_lds_sync();
-      // moments: the cursor piece in registers, later pieces of a crossing chunk by wave sums
-#pragma unroll
-      for (int j = 0; j < kCovMaxSpl; ++j) {
-        if (j >= n_spl) break;
-        const int cur = uniform(L.cur[j][0]);
-        if (cur < 0) continue;
-        const double g = L.gp[j][lane], tt = L.t[j][lane];
-        const int pc = L.pc[j][lane];
-        const double u1 = g * tt, u2 = u1 * tt;
-        const double v4[4] = {g, u1, u2, u2 * tt};
-        if (pc == cur) {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) acc[j][m] += v4[m];
-        }
-        const int hi = uniform(L.cur[j][1]);
-        for (int q = cur + 1; q <= hi; ++q) {
-          double sq[4];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) sq[m] = wave_sum(pc == q ? v4[m] : 0.0);
-          if (lane == 0) mo_add(mo + ((size_t)j * kMaxKnots + q) * 4, sq);
-        }
-      }
-      wave_lds_sync();
-    }
-    // finished pieces: flush the cursor piece and move the cursor
-#pragma unroll
-    for (int j = 0; j < kCovMaxSpl; ++j) {
-      if (j >= n_spl) break;
-      const int cur = uniform(L.cur[j][0]);
-      const int hi = uniform(L.cur[j][1]);
-      if (cur < 0 || hi == cur) continue;
-      double sq[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        sq[m] = wave_sum(acc[j][m]);
-        acc[j][m] = 0.0;
-      }
-      const int np = uniform(L.cur[j][2]);
-      const PieceRec pr = load_piece(A, ((size_t)s * kCovMaxSpl + j) * kMaxKnots, hi, np);
-      if (lane == 0) {
-        mo_add(mo + ((size_t)j * kMaxKnots + cur) * 4, sq);
-        L.rec[j] = pr;
-        L.cur[j][0] = hi;
-      }
-    }
-    wave_lds_sync();
-  }
-  // the last pieces
-#pragma unroll
-  for (int j = 0; j < kCovMaxSpl; ++j) {
-    if (j >= n_spl) break;
-    const int cur = uniform(L.cur[j][0]);
-    if (cur < 0) continue;
-    double sq[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) sq[m] = wave_sum(acc[j][m]);
-    if (lane == 0) mo_add(mo + ((size_t)j * kMaxKnots + cur) * 4, sq);
-  }
-  // state results
-  const double Ls = wave_sum(lsum);
-  if (__ballot(bad) != 0ull || !isfinite(Ls)) st |= LPS_ST_PSD;
-  if (lane == 0) {
-    logL[s] = st ? -INFINITY : -(Ls + c0[0]);
-    if (status_out) status_out[s] = st;
-  }
-  if (st) {
-    zero_outputs();
-    return;
-  }
-  const double Gwo = wave_sum(g_wo), Gwt = wave_sum(g_wt), Glin = wave_sum(g_lin), Glinx = wave_sum(g_linx);
-  const double Gfg = wave_sum(g_fg);
-  if (lane == 0) {
-    const double a_oms = A.params[LPS_P_AOMS * (size_t)A.n_states + s];
-    const double a_tm = A.params[LPS_P_ATM * (size_t)A.n_states + s];
-    dparams[LPS_P_AOMS * (size_t)A.n_states + s] = 2.0 * a_oms * Gwo;
-    dparams[LPS_P_ATM * (size_t)A.n_states + s] = 2.0 * a_tm * Gwt;
-    dparams[LPS_P_U * (size_t)A.n_states + s] = Glin;
-    dparams[LPS_P_ALPHA * (size_t)A.n_states + s] = Glinx;
-    if (n_params > 4) dparams[LPS_P_UFG * (size_t)A.n_states + s] = kLn10 * Gfg;
-  }
-  wave_lds_sync();   // the moment table written by lane 0 is read by every lane
-  BackLds& B = *reinterpret_cast<BackLds*>(&L.val[0][0]);
-  for (int j = 0; j < n_spl; ++j) {
-    int a, n;
-    knot_range(off, kcnt, s * n_spl + j, a, n);
-    if (n == 0) continue;
-    double M[4] = {0.0, 0.0, 0.0, 0.0};
-    if (lane + 1 < n)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) M[m] = mo[((size_t)j * kMaxKnots + lane) * 4 + m];
-    spline_backward_wave(lane, kx + a, ky + a, n, M, dky + a, dkx + a, B);
-  }
-}
+namespace covk {
 
 lps_status check_cov_states(const lps_cov_ctx* ctx, const lps_states* st) {
   if (!ctx || !st) return LPS_E_NULL;
@@ -872,8 +374,10 @@ CovArgs cov_args(const lps_cov_ctx* c, const lps_states* st) {
   return A;
 }
 
-}  // namespace
+}  // namespace covk
 }  // namespace lps
+
+using namespace lps::covk;
 
 extern "C" {
 
@@ -948,6 +452,7 @@ lps_status lps_cov_create(const lps_cov_desc* d, int device, lps_cov_ctx** out) 
   ok = ok && hipMalloc((void**)&c->partial, S * c->n_groups * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->sigma, (size_t)K * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->c0, sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->gmo, S * kCovMaxSpl * kMaxKnots * 4 * sizeof(double)) == hipSuccess;
   if (!ok) {
     lps_cov_destroy(c);
     return LPS_E_NOMEM;
@@ -969,7 +474,7 @@ lps_status lps_cov_destroy(lps_cov_ctx* c) {
   if (!c) return LPS_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->tab, c->bx, c->coef, c->npc, c->status, c->partial, c->sigma, c->c0};
+  void* ptrs[] = {c->tab, c->bx, c->coef, c->npc, c->status, c->partial, c->sigma, c->c0, c->gmo};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -994,24 +499,6 @@ lps_status lps_cov_loglike_batch(lps_cov_ctx* c, const lps_states* st, double* l
   if (e != hipSuccess) return device_status(e);
   hipLaunchKernelGGL(k_cov_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, c->n_groups, c->partial, c->c0,
                      c->status, logL, status);
-  return device_status(hipGetLastError());
-}
-
-lps_status lps_cov_loglike_grad_batch(lps_cov_ctx* c, const lps_states* st, double* logL, double* dparams,
-                                      double* dknot_x, double* dknot_y, uint32_t* status, void* stream) {
-  using namespace lps;
-  lps_status cs = check_cov_states(c, st);
-  if (cs != LPS_OK) return cs;
-  const int n = st->n_states;
-  if (n == 0) return LPS_OK;
-  if (!logL || !dparams) return LPS_E_NULL;
-  if (c->n_spl > 0 && (!dknot_x || !dknot_y)) return LPS_E_NULL;
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_cov_coeffs(c, st, s);
-  if (e != hipSuccess) return device_status(e);
-  const CovArgs A = cov_args(c, st);
-  hipLaunchKernelGGL(k_cov_grad, dim3((n + 3) / 4), dim3(256), 0, s, A, st->knot_off, st->knot_cnt, st->knot_x,
-                     st->knot_y, c->n_params, c->c0, logL, dparams, dknot_x, dknot_y, status);
   return device_status(hipGetLastError());
 }
 
