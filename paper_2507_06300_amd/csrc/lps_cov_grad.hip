@@ -46,8 +46,7 @@ struct CovGradLds {
   double gp[kCovB][kSlots][kWave];       // dlogL / d(slot argument)
   double t[kCovB][kCovMaxSpl][kWave];    // x - start of the bin's piece
   int pc[kCovB][kCovMaxSpl][kWave];      // the bin's piece
-  PieceRec rec[kCovMaxSpl];
-  int cur[kCovMaxSpl][3];                // cursor piece, last piece of this chunk, pieces
+  PieceRec rec[kCovMaxSpl];              // the piece under each spline's cursor
 };
 static_assert(sizeof(BackLds) <= sizeof(double) * kCovB * kSlots * kWave, "backward LDS aliases val");
 
@@ -100,23 +99,30 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
   for (int j = 0; j < n_spl; ++j)
 #pragma unroll
     for (int m = 0; m < 4; ++m) mo[((size_t)j * kMaxKnots + lane) * 4 + m] = 0.0;
-  // cursors at the first bin
+  // cursors at the first bin.  The cursor state is uniform and lives in
+  // scalar registers (the spline loops are unrolled): cur = piece under the
+  // cursor (-1: disabled spline), hi = last piece that this chunk reaches,
+  // npc = pieces, xn = start of the piece after the cursor.
   const double x_first = A.tab[kRx * kp];
-#pragma unroll 1
-  for (int j = 0; j < n_spl; ++j) {
-    const int np = A.npc[(size_t)s * kCovMaxSpl + j];
-    int cur = -1;
+  int cur[kCovMaxSpl], hi[kCovMaxSpl], npc[kCovMaxSpl];
+  double xn[kCovMaxSpl];
+#pragma unroll
+  for (int j = 0; j < kCovMaxSpl; ++j) {
+    cur[j] = -1;
+    hi[j] = -1;
+    npc[j] = 0;
+    xn[j] = INFINITY;
+    if (j >= n_spl) continue;
+    const int np = uniform(A.npc[(size_t)s * kCovMaxSpl + j]);
+    npc[j] = np;
     if (np > 0) {
       const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
       const double bl = lane < np ? A.bx[row + lane] : INFINITY;
-      cur = uniform(max(__popcll(__ballot(bl <= x_first)) - 1, 0));
-      const PieceRec pr = load_piece(A, row, cur, np);
+      cur[j] = uniform(max(__popcll(__ballot(bl <= x_first)) - 1, 0));
+      hi[j] = cur[j];
+      const PieceRec pr = load_piece(A, row, cur[j], np);
+      xn[j] = pr.xn;
       if (lane == 0) L.rec[j] = pr;
-    }
-    if (lane == 0) {
-      L.cur[j][0] = cur;
-      L.cur[j][1] = cur;
-      L.cur[j][2] = np;
     }
   }
 #pragma unroll
@@ -138,17 +144,15 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
     const double* tb = A.tab + kb + lane;
     const double xl = A.tab[kRx * kp + kb + kCovChunk - 1];
     // pieces that start inside this chunk
-#pragma unroll 1
-    for (int j = 0; j < n_spl; ++j) {
-      const int cur = uniform(L.cur[j][0]);
-      if (cur < 0 || !(xl >= L.rec[j].xn)) continue;
-      const int np = uniform(L.cur[j][2]);
+#pragma unroll
+    for (int j = 0; j < kCovMaxSpl; ++j) {
+      if (j >= n_spl) break;
+      if (cur[j] < 0 || !(xl >= xn[j])) continue;
       const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-      int hi = cur + 1;
-      while (hi + 1 < np && A.bx[row + hi + 1] <= xl) ++hi;
-      if (lane == 0) L.cur[j][1] = hi;
+      int h = cur[j] + 1;
+      while (h + 1 < npc[j] && A.bx[row + h + 1] <= xl) ++h;
+      hi[j] = h;
     }
-    wave_lds_sync();
     // the bins' table entries, loaded ahead of the LDS exchanges below (whose
     // fences would otherwise hold every load back until the spline work is done)
     RegRow row[kCovB];
@@ -161,24 +165,23 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
       lin[bb] = sc.u + sc.alpha * (x[bb] - A.x_knee);
     }
     // forward: slot values, the bin's piece and abscissa offset per spline
-#pragma unroll 1
-    for (int j = 0; j < n_spl; ++j) {
-      const int cur = uniform(L.cur[j][0]);
+#pragma unroll
+    for (int j = 0; j < kCovMaxSpl; ++j) {
+      if (j >= n_spl) break;
+      const int cur_j = cur[j];
       double pv[kCovB], tt[kCovB];
       int pc[kCovB];
-      if (cur >= 0) {
+      if (cur_j >= 0) {
         PieceRec pr[kCovB];
 #pragma unroll
         for (int bb = 0; bb < kCovB; ++bb) {
           pr[bb] = L.rec[j];
-          pc[bb] = cur;
+          pc[bb] = cur_j;
         }
-        const int hi = uniform(L.cur[j][1]);
-        if (hi != cur) {
+        if (hi[j] != cur_j) {
           const size_t rw = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-          const int np = uniform(L.cur[j][2]);
-          for (int q = cur + 1; q <= hi; ++q) {
-            const PieceRec nq = load_piece(A, rw, q, np);
+          for (int q = cur_j + 1; q <= hi[j]; ++q) {
+            const PieceRec nq = load_piece(A, rw, q, npc[j]);
 #pragma unroll
             for (int bb = 0; bb < kCovB; ++bb)
               if (x[bb] >= nq.x0) {
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
         for (int bb = 0; bb < kCovB; ++bb) {
           pv[bb] = 0.0;
           tt[bb] = 0.0;
-          pc[bb] = cur;
+          pc[bb] = cur_j;
         }
       }
 #pragma unroll
@@ -279,8 +282,7 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
 #pragma unroll
     for (int j = 0; j < kCovMaxSpl; ++j) {
       if (j >= n_spl) break;
-      const int cur = uniform(L.cur[j][0]);
-      if (cur < 0) continue;
+      if (cur[j] < 0) continue;
       double v4[kCovB][4];
       int pc[kCovB];
 #pragma unroll
@@ -293,10 +295,9 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
         v4[bb][2] = u2;
         v4[bb][3] = u2 * tt;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc[j][m] += pc[bb] == cur ? v4[bb][m] : 0.0;
+        for (int m = 0; m < 4; ++m) acc[j][m] += pc[bb] == cur[j] ? v4[bb][m] : 0.0;
       }
-      const int hi = uniform(L.cur[j][1]);
-      for (int q = cur + 1; q <= hi; ++q) {
+      for (int q = cur[j] + 1; q <= hi[j]; ++q) {
         double sq[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -313,22 +314,18 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
 #pragma unroll
     for (int j = 0; j < kCovMaxSpl; ++j) {
       if (j >= n_spl) break;
-      const int cur = uniform(L.cur[j][0]);
-      const int hi = uniform(L.cur[j][1]);
-      if (cur < 0 || hi == cur) continue;
+      if (cur[j] < 0 || hi[j] == cur[j]) continue;
       double sq[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         sq[m] = wave_sum(acc[j][m]);
         acc[j][m] = 0.0;
       }
-      const int np = uniform(L.cur[j][2]);
-      const PieceRec pr = load_piece(A, ((size_t)s * kCovMaxSpl + j) * kMaxKnots, hi, np);
-      if (lane == cur) mo_add(mo + ((size_t)j * kMaxKnots + cur) * 4, sq);
-      if (lane == 0) {
-        L.rec[j] = pr;
-        L.cur[j][0] = hi;
-      }
+      const PieceRec pr = load_piece(A, ((size_t)s * kCovMaxSpl + j) * kMaxKnots, hi[j], npc[j]);
+      if (lane == cur[j]) mo_add(mo + ((size_t)j * kMaxKnots + cur[j]) * 4, sq);
+      if (lane == 0) L.rec[j] = pr;
+      cur[j] = hi[j];
+      xn[j] = pr.xn;
     }
     wave_lds_sync();
   }
@@ -336,12 +333,11 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
 #pragma unroll
   for (int j = 0; j < kCovMaxSpl; ++j) {
     if (j >= n_spl) break;
-    const int cur = uniform(L.cur[j][0]);
-    if (cur < 0) continue;
+    if (cur[j] < 0) continue;
     double sq[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) sq[m] = wave_sum(acc[j][m]);
-    if (lane == cur) mo_add(mo + ((size_t)j * kMaxKnots + cur) * 4, sq);
+    if (lane == cur[j]) mo_add(mo + ((size_t)j * kMaxKnots + cur[j]) * 4, sq);
   }
   // state results
   const double Ls = wave_sum(lsum);
