@@ -228,27 +228,38 @@ COV_SOURCES = ["paper_2507_06300_amd/csrc/lps_cov.hip", "paper_2507_06300_amd/cs
                "paper_2507_06300_amd/csrc/lps_templates.hpp",
                "paper_2507_06300_amd/csrc/lps_math64.hpp"]
 COV_PROFILE = "profiles/k_cov_eval_year_912085bins_4096states.md"
+COV_GRAD_SOURCES = ["paper_2507_06300_amd/csrc/lps_cov_grad.hip", "paper_2507_06300_amd/csrc/lps_cov_common.hpp",
+                    "paper_2507_06300_amd/csrc/lps_spline_back.hpp", "paper_2507_06300_amd/csrc/lps_math64.hpp"]
+COV_GRAD_PROFILE = "profiles/k_cov_grad_year_912085bins_4096states.md"
 
 
-def profiled_cov_valu():
-    """VALU lane-instructions per state.bin of the covariance kernel from the
-    committed counter summary, or None if the kernel source changed since."""
+def _profiled_valu(profile, sources, key):
+    """VALU lane-instructions per state.bin of a kernel from its committed
+    counter summary, or None if the kernel's sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, COV_PROFILE)
+    path = os.path.join(ROOT, profile)
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in COV_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     fields = {}
     for line in open(path):
         if ":" in line and line.startswith("    ") and "_" in line.split(":")[0]:
             k, v = line.strip().split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("cov_source_sha256_16") != h.hexdigest()[:16]:
+    if fields.get(key) != h.hexdigest()[:16]:
         return None
     v = fields.get("valu_lane_instr_per_state_bin")
     return float(v) if v else None
+
+
+def profiled_cov_valu():
+    return _profiled_valu(COV_PROFILE, COV_SOURCES, "cov_source_sha256_16")
+
+
+def profiled_cov_grad_valu():
+    return _profiled_valu(COV_GRAD_PROFILE, COV_GRAD_SOURCES, "cov_grad_source_sha256_16")
 
 
 def _cov_states(W, ds, name, rng_seed):
@@ -296,11 +307,20 @@ def cov_bench(torch, lps, W, args, dev):
     per_g = tg / steps
     log(f"cov adjoint: {per_g * 1e3:.2f} ms/call, {n * K / per_g:.3e} state.bin/s")
     ctx.close()
+    gv = profiled_cov_grad_valu()
+    grad_roof = None
+    if gv is not None:
+        # issue-bound FP64 arithmetic: achieved = wave instructions per second
+        wi = gv * n * K / 64.0 / per_g
+        grad_roof = {"bound": "alu", "achieved": round(wi, 1), "peak": PEAK_FP64_WAVE_INSTR_PER_S,
+                     "unit": "FP64 VALU wave instructions/s", "frac": round(wi / PEAK_FP64_WAVE_INSTR_PER_S, 4),
+                     "valu_lane_instr_per_state_bin": gv}
     valu = profiled_cov_valu()
     issue = None if valu is None else valu * n * K / 64.0 / per / PEAK_FP64_WAVE_INSTR_PER_S
     return {"workload": name, "layout": COV_LAYOUT, "n_bins": K, "n_states": n, "splines_per_state": nb + 3,
             "grad": {"ms_per_call": per_g * 1e3, "state_bin_grad_evals_per_s": n * K / per_g,
-                     "timed": "whole call (coefficients + adjoint + spline backward), graph replays"},
+                     "timed": "whole call (coefficients + adjoint + spline backward), graph replays",
+                     "roofline": grad_roof},
             "correlation_in_between_knots": list(COV_CORR_INBETWEEN), "dtype": "f64",
             "value": n * K / per, "unit": UNIT, "ms_per_call": per * 1e3, "valid_states": valid,
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
