@@ -374,7 +374,7 @@ typedef struct {
                             (term, channel); route[LPS_TERM_FG][*] must be -1 */
   int8_t corr[3];        /* slots of Q_0 (A-E), Q_1 (A-T), Q_2 (E-T given A), or -1 */
   int32_t k_max;         /* max knots per spline including edges, 2..64 */
-  int32_t max_states;    /* workspace capacity in states (>= 1); about 42 KB per state */
+  int32_t max_states;    /* workspace capacity in states (>= 1); about 37 KB per state */
 } lps_cov_desc;
 
 /* Create a full-covariance context on `device`: copies the data into a per-bin
