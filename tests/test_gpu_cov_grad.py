@@ -224,3 +224,45 @@ def test_full_year_grid_sampled(lps):
     # the oracle there)
     assert np.all(np.abs(logL[ok] - ev[ok]) <= 1e-9 * np.abs(ev[ok]))
     assert np.all(logL[~ok] == -math.inf)
+
+
+def test_batch_independence_and_graph_replay(lps):
+    """A state's results do not depend on the batch it is evaluated in, and the
+    call captured into a HIP graph and replayed (eager calls in between) gives
+    the eager result every time."""
+    name = "avg50_1000bins_64states"
+    _say("cov grad batch independence and graph replay")
+    ds, cds, P6, sb = _setup(name, 1000, "paper", 24, seed=9)
+    ctx = _ctx(lps, ds, cds, P6, sb.n)
+    st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
+    full = [t.clone() for t in ctx.loglike_grad_batch(st)]
+    fl = full[0].cpu().numpy()
+    fdp = full[1].cpu().numpy()
+    fkx, fky = full[2].cpu().numpy(), full[3].cpu().numpy()
+    for idx in ([5], [23, 0, 17], list(range(8, 20))):
+        sub = W.states_subset(sb, idx)
+        l, dp, dkx, dky, _ = ctx.loglike_grad_batch(ctx.states(sub.params, sub.knot_off, sub.knot_x, sub.knot_y))
+        assert np.array_equal(l.cpu().numpy(), fl[idx])
+        assert np.array_equal(dp.cpu().numpy(), fdp[:, idx])
+        dkx, dky = dkx.cpu().numpy(), dky.cpu().numpy()
+        for i, s in enumerate(idx):
+            gy, gx = _unpack(sub, i, dkx, dky)
+            ry, rx = _unpack(sb, s, fkx, fky)
+            assert all(np.array_equal(a, b) for a, b in zip(gy + gx, ry + rx))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.loglike_grad_batch(st, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        outs = ctx.loglike_grad_batch(st)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, f in zip(outs, full):
+            assert torch.equal(o, f), rep
+        assert torch.equal(ctx.loglike_grad_batch(st)[1], full[1])
