@@ -59,6 +59,20 @@ namespace {
 
 using namespace covk;
 
+// Orders the LDS accesses of one wavefront's lanes (lane 0 writes, all read).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ void k_cov_table(int K, int k_pad, const double* __restrict__ f, const double* __restrict__ nk,
                             const double* __restrict__ P, const double* __restrict__ R,
                             const double* __restrict__ Rfg, double L, double* __restrict__ tab,
@@ -184,7 +198,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
   }
 
+  wave_sync();
   double acc = 0.0;   // lane i: the sum of state s0 + i over this group
+  int* const lcur_w = &lcur[w][0][0][0];
   for (int ch = c_begin; ch < c_end; ++ch) {
     const int kb = ch * kCovChunk;
     const double* tb = A.tab + kb + lane;   // row r, bin b of the chunk: tb[r * kp + b * kWave]
@@ -193,16 +209,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       const int s = s0 + i;
       if (A.status[s] != 0u) continue;
       const StateScal sc = state_scalars(A.params, A.n_states, s, A.has_fg);
+      // the state's cursors in one register: lane 3j + q holds field q of
+      // spline j (cursor piece, last piece this chunk, pieces), lane j the
+      // start of the piece after spline j's cursor; read by lane index, so
+      // no uniform branch below waits on LDS
+      int* const lc = lcur_w + i * kCovMaxSpl * 3;
+      int cv = lane < 3 * kCovMaxSpl ? lc[lane] : 0;
+      const double xnv = lane < kCovMaxSpl ? lrec[w][i][lane].xn : 0.0;
       // pieces that start inside this chunk
 #pragma unroll 1
       for (int j = 0; j < A.n_spl; ++j) {
-        const int cur = uniform(lcur[w][i][j][0]);
-        if (cur < 0 || !(xl >= lrec[w][i][j].xn)) continue;
-        const int np = uniform(lcur[w][i][j][2]);
+        const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+        if (cur < 0 || !(xl >= readlane_d(xnv, j))) continue;
+        const int np = __builtin_amdgcn_readlane(cv, 3 * j + 2);
         const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
         int hi = cur + 1;
         while (hi + 1 < np && A.bx[row + hi + 1] <= xl) ++hi;
-        if (lane == 0) lcur[w][i][j][1] = hi;
+        cv = lane == 3 * j + 1 ? hi : cv;
       }
       double v = 0.0;
       bool bad = false;
@@ -212,14 +235,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         const double lin = sc.u + sc.alpha * (x - A.x_knee);
 #pragma unroll 1
         for (int j = 0; j < A.n_spl; ++j) {
-          const int cur = uniform(lcur[w][i][j][0]);
+          const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
           double pv = 0.0;
           if (cur >= 0) {
             PieceRec pr = lrec[w][i][j];
-            const int hi = uniform(lcur[w][i][j][1]);
+            const int hi = __builtin_amdgcn_readlane(cv, 3 * j + 1);
             if (hi != cur) {
               const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-              const int np = uniform(lcur[w][i][j][2]);
+              const int np = __builtin_amdgcn_readlane(cv, 3 * j + 2);
               for (int q = cur + 1; q <= hi; ++q) {
                 const PieceRec nq = load_piece(A, row, q, np);
                 if (x >= nq.x0) pr = nq;
@@ -238,16 +261,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       // move the cursors to the piece of the chunk's last bin
 #pragma unroll 1
       for (int j = 0; j < A.n_spl; ++j) {
-        const int cur = uniform(lcur[w][i][j][0]);
-        const int hi = uniform(lcur[w][i][j][1]);
+        const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+        const int hi = __builtin_amdgcn_readlane(cv, 3 * j + 1);
         if (hi == cur) continue;
-        const int np = uniform(lcur[w][i][j][2]);
+        const int np = __builtin_amdgcn_readlane(cv, 3 * j + 2);
         const PieceRec pr = load_piece(A, ((size_t)s * kCovMaxSpl + j) * kMaxKnots, hi, np);
-        if (lane == 0) {
-          lrec[w][i][j] = pr;
-          lcur[w][i][j][0] = hi;
-        }
+        if (lane == 0) lrec[w][i][j] = pr;
+        cv = lane == 3 * j ? hi : cv;
       }
+      if (lane < 3 * kCovMaxSpl) lc[lane] = cv;
+      wave_sync();
       if (__ballot(bad) != 0ull && lane == 0) atomicOr(&A.status[s], (unsigned)LPS_ST_PSD);
       v = wave_sum(v);
       acc = lane == i ? acc + v : acc;
