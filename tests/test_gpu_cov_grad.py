@@ -266,3 +266,29 @@ def test_batch_independence_and_graph_replay(lps):
         for o, f in zip(outs, full):
             assert torch.equal(o, f), rep
         assert torch.equal(ctx.loglike_grad_batch(st)[1], full[1])
+
+
+def test_disabled_and_linear_splines(lps):
+    """Correlation splines with no knots (Q = 0), two or three knots (the
+    linear construction) and the Akima construction mixed in one batch."""
+    name = "avg50_1000bins_64states"
+    _say("cov grad disabled and linear splines")
+    ds, cds, P6, sb = _setup(name, 900, "paper", 6, seed=11)
+    x_lo, x_hi = W.band_edges(ds.f)
+    rng = np.random.default_rng(12)
+    knots = []
+    for s in range(sb.n):
+        kn = _knots(sb, s)
+        for j in range(ds.n_spl, sb.n_spl):
+            m = (s + j) % 4           # 0, 2, 3 knots or the drawn Akima spline
+            if m == 0:
+                kn[j] = (np.zeros(0), np.zeros(0))
+            elif m in (1, 2):
+                n = m + 1
+                inner = np.sort(rng.uniform(x_lo, x_hi, n - 2))
+                kn[j] = (np.concatenate([[x_lo], inner, [x_hi]]), rng.normal(0.0, 0.5, n))
+        knots.append(kn)
+    sbx = W.pack_states(sb.params, knots, sb.n_spl)
+    ctx = _ctx(lps, ds, cds, P6, sbx.n)
+    _, _, status = _check_batch(ctx, cds, P6, sbx, range(sbx.n), "disabled/linear")
+    assert np.all(status == 0)
