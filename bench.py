@@ -62,6 +62,12 @@ def profiled_traffic(workload, shape):
     """HBM bytes per launch of the mixed forward kernel from the committed
     rocprofv3 PMC summary, or None if the kernel sources or the launch shape
     differ from what was profiled (the counters then describe another kernel)."""
+    return profiled_forward_field(workload, f"traffic_bytes_per_launch_mixed_{shape[0]}x{shape[1]}")
+
+
+def profiled_forward_field(workload, key):
+    """A machine-readable field of the committed forward-kernel summary, or None
+    if the kernel sources no longer hash to the profiled ones."""
     import hashlib
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if workload != "year_912085bins_4096states" or not os.path.exists(path):
@@ -76,8 +82,22 @@ def profiled_traffic(workload, shape):
             fields[k.strip()] = v.strip()
     if fields.get("forward_source_sha256_16") != h.hexdigest()[:16]:
         return None
-    key = f"traffic_bytes_per_launch_mixed_{shape[0]}x{shape[1]}"
     return float(fields[key]) if key in fields else None
+
+
+def fp64_roofline(workload, state_bins, s_per_call):
+    """Issue share of the FP64 batched forward from the committed counter summary
+    (VALU lane-instructions per state.bin, every one counted at the FP64 rate),
+    or None if the kernel sources changed since they were counted."""
+    v = profiled_forward_field(workload, "valu_lane_instr_per_state_bin_fp64")
+    if v is None:
+        return None
+    wi = v * state_bins / 64.0 / s_per_call
+    return {"bound": "alu", "achieved": round(wi, 1), "peak": PEAK_FP64_WAVE_INSTR_PER_S,
+            "unit": "FP64 VALU wave instructions/s", "frac": round(wi / PEAK_FP64_WAVE_INSTR_PER_S, 4),
+            "valu_lane_instr_per_state_bin": v,
+            "timed": "whole call (coefficients + forward + finalize); an upper bound on the issue share, since "
+                     "32-bit instructions issue faster than FP64 ones"}
 
 
 def log(*a):
@@ -487,7 +507,8 @@ def main():
                          "N_k": wl.nk, "in_between_knots": list(wl.inbetween), "layout": ds.layout,
                          "precision": "mixed"},
               "roofline": roofline,
-              "fp64_batched": {"value": fp64_value, "unit": UNIT, "ms_per_call": t64 / steps64 * 1e3},
+              "fp64_batched": {"value": fp64_value, "unit": UNIT, "ms_per_call": t64 / steps64 * 1e3,
+                               "roofline": fp64_roofline(name, n * K, t64 / steps64)},
               "launch_shapes": shapes,
               "mixed_error": mixed_err}
 
