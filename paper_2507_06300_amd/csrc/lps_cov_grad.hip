@@ -4,8 +4,6 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include <type_traits>
-
 #include "lps.h"
 #include "lps_internal.hpp"
 #include "lps_math64.hpp"
@@ -40,7 +38,8 @@ using namespace covk;
 // Per wave; the kCovB bins of a lane go through each phase together (their
 // arithmetic is independent, which gives the scheduler two chains to
 // interleave).  Slots kSlotOne and kSlotZero of gp collect the derivatives
-// of terms that no spline perturbs; they are never read.
+// of terms that no spline perturbs; they are never read.  val, gp, t and pc
+// are lane-private columns; rec is written by lane 0 and read by every lane.
 struct CovGradLds {
   double val[kCovB][kSlots][kWave];      // slot values of the lane's bins
   double gp[kCovB][kSlots][kWave];       // dlogL / d(slot argument)
@@ -60,7 +59,8 @@ __device__ inline void mo_add(double* __restrict__ m, const double (&v)[4]) {
   for (int i = 0; i < 4; ++i) m[i] += v[i];
 }
 
-__global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict__ mo_ws, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+__global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict__ mo_ws,
+                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
                                                   const double* __restrict__ kx, const double* __restrict__ ky,
                                                   int n_params, const double* __restrict__ c0,
                                                   double* __restrict__ logL, double* __restrict__ dparams,
