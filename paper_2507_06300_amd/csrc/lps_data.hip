@@ -40,15 +40,31 @@ __global__ void k_prep_series(int n_ch, int n, const double* __restrict__ x, con
   }
 }
 
-// mean(w^2) in one block, fixed order (1 when there is no window)
-__global__ __launch_bounds__(256) void k_window_power(int n, const double* __restrict__ w, double* __restrict__ out) {
+// mean(w^2) in two fixed-order stages (1 when there is no window): kWinParts
+// blocks each add a grid-strided share of w^2, then one block adds the partials.
+constexpr int kWinParts = 256;
+
+__global__ __launch_bounds__(256) void k_window_part(int n, const double* __restrict__ w,
+                                                     double* __restrict__ part) {
   __shared__ double sh[256];
   double acc = 0.0;
   if (w)
-    for (int i = threadIdx.x; i < n; i += 256) acc += w[i] * w[i];
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kWinParts * 256) acc += w[i] * w[i];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_window_power(int n, const double* __restrict__ w,
+                                                      const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kWinParts];
+  sh[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int s = kWinParts / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
@@ -131,7 +147,7 @@ lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, doub
   bool have_plan = false;
   hipError_t e = hipMalloc((void**)&xw, (size_t)n_ch * n_t * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&X, (size_t)n_ch * nf * sizeof(hipfftDoubleComplex));
-  if (e == hipSuccess) e = hipMalloc((void**)&w2, sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&w2, (1 + lps::kWinParts) * sizeof(double));   // mean, partials
   lps_status st = LPS_OK;
   if (e != hipSuccess) st = LPS_E_NOMEM;
   if (st == LPS_OK) {
@@ -147,7 +163,8 @@ lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, doub
   if (st == LPS_OK) {
     hipLaunchKernelGGL(lps::k_prep_series, lps::blocks_for(n_t, 256), dim3(256), 0, s, n_ch, n_t, x, window,
                        xyz_to_aet, xw);
-    hipLaunchKernelGGL(lps::k_window_power, dim3(1), dim3(256), 0, s, n_t, window, w2);
+    hipLaunchKernelGGL(lps::k_window_part, dim3(lps::kWinParts), dim3(256), 0, s, n_t, window, w2 + 1);
+    hipLaunchKernelGGL(lps::k_window_power, dim3(1), dim3(lps::kWinParts), 0, s, n_t, window, w2 + 1, w2);
     if (hipfftExecD2Z(plan, (hipfftDoubleReal*)xw, X) != HIPFFT_SUCCESS) st = LPS_E_DEVICE;
   }
   if (st == LPS_OK) {
