@@ -386,7 +386,8 @@ def main():
     EAGER = args.eager
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by walker; see the design notes)", file=sys.stderr)
+              "(states are independent: the path would shard by walker, each GPU holding a replica of the "
+              "per-bin tables, with no communication per likelihood call)", file=sys.stderr)
         sys.exit(2)
     # CPU legs first: their worker processes are forked before this process
     # initialises the GPU
