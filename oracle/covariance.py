@@ -8,8 +8,8 @@ treatment as the natural extension (Sec. "Power spectral density breakdown",
 the paragraph on independent channel splines, and the outlook of the
 conclusions): three more flexible terms for the off-diagonal entries, six
 flexible functions in all, combined so that the covariance stays Hermitian
-positive definite.  It does not print the construction.  Reading X1 (listed
-with its reasons in the design notes) fixes one:
+positive definite.  It does not print the construction.  Reading X1 fixes
+one:
 
   frame        A/E/T.  The likelihood below is unchanged under any orthonormal
                change of channel basis applied to both the model and the data,

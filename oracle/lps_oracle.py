@@ -13,8 +13,8 @@ the averaged-periodogram likelihood, and App. A for the Akima spline):
   S_c(f_k | theta) = sum over terms tau of  template_tau,c(f_k) * 10**P_{route[tau][c]}(x_k)
   logL(theta)      = - sum_c sum_k N_k (D_ck / S_ck + ln S_ck)
 
-with x_k = log10 f_k.  Readings of passages that are ambiguous or garbled
-(each is listed with its reason in the design notes):
+with x_k = log10 f_k.  Readings of passages that are ambiguous or garbled,
+each with its reason:
 
   R1  TDI prefactor of Eq. (noise_tdi): sin^2(xi) * sin^2(2 xi), xi = 2 pi f L / c.
       (Printed as sin^2 * sin^4; the X2 delay polynomial of Sec. "Time-delay

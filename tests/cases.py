@@ -43,7 +43,7 @@ def device_states(ctx, sb):
 
 
 def mixed_tolerance(ds, D, sb, idx):
-    """Derived bound for the mixed path (see the design notes).
+    """Derived bound for the mixed path.
 
     Each per-bin term N_k (D/S + ln S~) is formed from single-precision
     operations whose combined relative error is a few tens of units of
