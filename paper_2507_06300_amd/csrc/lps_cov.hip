@@ -32,15 +32,19 @@
 // Work decomposition: the coefficient kernel validates every state and
 // stores the cubic pieces of its splines (one wave per state, one lane per
 // piece).  In the evaluation kernel a workgroup of four waves takes one group
-// of consecutive 128-bin chunks and four tiles of states: it stages each
-// chunk's table rows in LDS once, and every wave then runs through the states
-// of its tile on them.  A spline's pieces over a chunk are found with two
-// ballots over the piece abscissae (lane = piece); usually one piece covers
-// the chunk and its coefficients are uniform loads.  Spline values go through
-// LDS so that the spline loop need not be unrolled.  Each wave keeps the sum
-// of state i of its tile in lane i; partial sums per (state, chunk group) are
-// added in a fixed order by the finalize kernel, so results do not depend on
-// the batch size.
+// of consecutive 128-bin chunks and four tiles of up to eight states; every
+// wave runs through the states of its tile on each chunk, reading the chunk's
+// table rows from memory (the four waves share them in L1).  Each (state,
+// spline) has a cursor: the piece holding the chunk's first bin, found by a
+// ballot over the piece abscissae (lane = piece) at the start of the group
+// and advanced chunk by chunk; a chunk that reaches further pieces loads
+// their records and selects per bin.  A state's cursors are read into one
+// register and picked by lane index.  Spline values go through LDS so that
+// the spline loop need not be unrolled.  Each wave keeps the sum of state i
+// of its tile in lane i; partial sums per (state, chunk group) are added in a
+// fixed order by the finalize kernel, so results do not depend on the batch
+// size.  The adjoint (lps_cov_grad.hip) shares the model code through
+// lps_cov_common.hpp.
 #include <math.h>
 #include <string.h>
 
