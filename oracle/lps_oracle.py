@@ -83,12 +83,15 @@ def noise_tdi(f, arm_length, A_oms, A_tm):
     xi = 2.0 * math.pi * f * arm_length / C_LIGHT
     pref = np.sin(xi) ** 2 * np.sin(2.0 * xi) ** 2
     cx = np.cos(xi)
+    # 1 - cos(xi) written as 2 sin^2(xi/2): the same quantity without the
+    # cancellation that costs 1 - cos(xi) five digits at 0.1 mHz
+    omc = 2.0 * np.sin(0.5 * xi) ** 2
     so = s_oms(f, A_oms)
     st = s_tm(f, A_tm)
     ae_oms = 32.0 * pref * (2.0 + cx) * so
     ae_tm = 32.0 * pref * 4.0 * (1.0 + cx + cx ** 2) * st
-    t_oms = 64.0 * pref * (1.0 - cx) * so
-    t_tm = 64.0 * pref * 2.0 * (1.0 - cx) ** 2 * st
+    t_oms = 64.0 * pref * omc * so
+    t_tm = 64.0 * pref * 2.0 * omc ** 2 * st
     return np.stack([ae_oms, ae_oms, t_oms]), np.stack([ae_tm, ae_tm, t_tm])
 
 

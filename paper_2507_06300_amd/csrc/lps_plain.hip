@@ -58,14 +58,16 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
     const double xi = 2.0 * kPi * fk * L / kClight;
     const double sx = sin(xi), cx = cos(xi), s2x = sin(2.0 * xi);
     const double pref = sx * sx * s2x * s2x;
+    const double sh = sin(0.5 * xi);
+    const double omc = 2.0 * sh * sh;   // 1 - cos xi without cancellation
     const double s_oms = a_oms * a_oms * (1.0 + pow(2.0e-3 / fk, 4.0)) * pow(2.0 * kPi * fk / kClight, 2.0);
     const double s_tm = a_tm * a_tm * (1.0 + pow(0.4e-3 / fk, 2.0)) * (1.0 + pow(fk / 8.0e-3, 4.0)) *
                         pow(2.0 * kPi * fk * kClight, -2.0);
     const double oms[3] = {32.0 * pref * (2.0 + cx) * s_oms, 32.0 * pref * (2.0 + cx) * s_oms,
-                           64.0 * pref * (1.0 - cx) * s_oms};
+                           64.0 * pref * omc * s_oms};
     const double tm[3] = {32.0 * pref * 4.0 * (1.0 + cx + cx * cx) * s_tm,
                           32.0 * pref * 4.0 * (1.0 + cx + cx * cx) * s_tm,
-                          64.0 * pref * 2.0 * (1.0 - cx) * (1.0 - cx) * s_tm};
+                          64.0 * pref * 2.0 * omc * omc * s_tm};
     const double h2omega = exp10(u) * pow(fk / f_knee, alpha);
     const double hfac = h2omega * 3.0 * kH0PerH * kH0PerH / (4.0 * kPi * kPi * fk * fk * fk);
     double P[4] = {0.0, 0.0, 0.0, 0.0};

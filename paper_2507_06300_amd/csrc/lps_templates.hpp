@@ -24,8 +24,11 @@ __device__ inline void unit_templates(double fk, double L, double& oms_ae, doubl
   const double s_tm = (1.0 + r4 * r4) * (1.0 + r8 * r8 * r8 * r8) * q * q;
   oms_ae = 32.0 * pref * (2.0 + cx) * s_oms;
   tm_ae = 32.0 * pref * 4.0 * (1.0 + cx + cx * cx) * s_tm;
-  oms_t = 64.0 * pref * (1.0 - cx) * s_oms;
-  tm_t = 64.0 * pref * 2.0 * (1.0 - cx) * (1.0 - cx) * s_tm;
+  // 1 - cos xi as 2 sin^2(xi/2), free of cancellation at low frequency
+  const double sh = sin(0.5 * xi);
+  const double omc = 2.0 * sh * sh;
+  oms_t = 64.0 * pref * omc * s_oms;
+  tm_t = 64.0 * pref * 2.0 * omc * omc * s_tm;
   h = 3.0 * kH0PerH * kH0PerH / (4.0 * kPi * kPi * fk * fk * fk);
 }
 

@@ -247,3 +247,52 @@ def test_mutation_cov_gradient_copy_is_faithful(monkeypatch):
     comes from the planted mistake alone)."""
     monkeypatch.setattr(CV, "_covariance_tangent", _tangent_with(None))
     assert not _cov_grad_pins_fail()
+
+
+# ---------------------------------------------------------------------------
+# Single-link noise shapes: corner frequencies and bracket exponents
+# ---------------------------------------------------------------------------
+
+import tests.test_oracle_noise_shapes as shapes   # noqa: E402
+
+_SHAPE_PINS = [shapes.test_oms_is_the_printed_laurent_polynomial, shapes.test_tm_is_the_printed_laurent_polynomial,
+               shapes.test_brackets_double_at_their_corners, shapes.test_asymptotic_log_slopes]
+
+
+def _shape_pins_fail():
+    return any(_fails(p) for p in _SHAPE_PINS)
+
+
+def _tm_variant(f_lo, f_hi, hi_exp):
+    def s_tm(f, A_tm):
+        return (A_tm ** 2 * (1.0 + (f_lo / f) ** 2) * (1.0 + (f / f_hi) ** hi_exp)
+                * (1.0 / (2.0 * math.pi * f * O.C_LIGHT)) ** 2)
+    return s_tm
+
+
+def _oms_variant(f_c, exp):
+    def s_oms(f, A_oms):
+        return A_oms ** 2 * (1.0 + (f_c / f) ** exp) * (2.0 * math.pi * f / O.C_LIGHT) ** 2
+    return s_oms
+
+
+def test_shape_pins_pass_on_faithful_copies(monkeypatch):
+    # the variant builders reproduce the oracle exactly at the printed values
+    monkeypatch.setattr(O, "s_tm", _tm_variant(0.4e-3, 8.0e-3, 4))
+    monkeypatch.setattr(O, "s_oms", _oms_variant(2.0e-3, 4))
+    assert not _shape_pins_fail()
+
+
+@pytest.mark.parametrize("variant", [(0.4e-3, 8.0e-3, 2),    # high bracket (f / 8 mHz)^2
+                                     (0.4e-3, 4.0e-3, 4),    # high corner 4 mHz
+                                     (4.0e-3, 8.0e-3, 4)])   # low corner 4 mHz
+def test_mutation_tm_shape(monkeypatch, variant):
+    monkeypatch.setattr(O, "s_tm", _tm_variant(*variant))
+    assert _shape_pins_fail()
+
+
+@pytest.mark.parametrize("variant", [(3.0e-3, 4),            # OMS corner 3 mHz
+                                     (2.0e-3, 2)])           # OMS bracket exponent 2
+def test_mutation_oms_shape(monkeypatch, variant):
+    monkeypatch.setattr(O, "s_oms", _oms_variant(*variant))
+    assert _shape_pins_fail()
