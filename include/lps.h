@@ -179,6 +179,26 @@ lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st /*[host]*/,
                                   uint32_t* status, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+ * FP64 path of lps_loglike_plain_fp64 without a context.  desc [host] names
+ * the dataset's device arrays directly (f, nk, D, R, Rfg as in lps_create;
+ * max_states and max_grad_states are ignored; any routing whose slots are in
+ * [-1, n_spl) with route[LPS_TERM_FG][*] = -1 is accepted), and nothing is
+ * copied, built or allocated: the per-block partial sums live in a 512 KiB
+ * device-resident array that each GPU holds for the life of the process.
+ * Limits: n_bins <= 2^24 (LPS_E_CAPACITY beyond), k_max in [2, 64].
+ * f must be strictly increasing and positive (not checked: no host copy is
+ * made).  States, outputs, status bits and errors as lps_loglike_plain_fp64;
+ * results are identical to it for the same inputs.  All calls on one GPU
+ * share the array (the last call's contents stay in it; every entry a call
+ * reads it writes first): calls that overlap in time on one GPU, on any
+ * streams or host threads, race and must be serialised by the caller.
+ */
+lps_status lps_loglike_plain_fp64_noalloc(const lps_dataset_desc* desc /*[host]*/, const lps_states* st /*[host]*/,
+                                          double* logL, uint32_t* status, void* stream);
+
+/*
  * Launch shape of the batched forward kernel for one precision: bins per lane
  * (the wave's chunk is 64 times that; mixed: 4 or 8, FP64: 2 or 4) and states
  * per work item (1..4096).  0 selects the built-in default (mixed 8, FP64 4;

@@ -73,7 +73,7 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_stepping_stone", "lps_dic",
            "lps_data_periodogram", "lps_data_average", "lps_data_response",
            "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch", "lps_cov_build",
-           "lps_math64_check"]
+           "lps_math64_check", "lps_loglike_plain_fp64_noalloc"]
 
 _lib = None
 
@@ -130,11 +130,12 @@ def lib():
     L.lps_cov_loglike_grad_batch.argtypes = [vp, ctypes.POINTER(_States), vp, vp, vp, vp, vp, vp]
     L.lps_cov_build.argtypes = [vp, ctypes.POINTER(_States), i32, i32, vp, vp, vp]
     L.lps_math64_check.argtypes = [vp, i32, i32, vp, vp]
+    L.lps_loglike_plain_fp64_noalloc.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_States), vp, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
                  "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response",
                  "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch",
-                 "lps_cov_build", "lps_math64_check"]:
+                 "lps_cov_build", "lps_math64_check", "lps_loglike_plain_fp64_noalloc"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -195,6 +196,36 @@ def _dev(a, dtype, device):
 def _stream(stream):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def loglike_plain_fp64_noalloc(f, nk, D, R, route, n_spl, st: "States", Rfg=None, k_max=64, f_knee=1.0e-3,
+                               arm_length=2.5e9, logL=None, status=None, stream=None):
+    """lps_loglike_plain_fp64_noalloc: the plain FP64 path without a context.
+
+    f, nk, D, R (and Rfg) must already be contiguous float64 device tensors;
+    the call itself allocates nothing on the device (outputs are allocated
+    here only when not given)."""
+    for t in (f, nk, D, R) + (() if Rfg is None else (Rfg,)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("dataset arrays must be contiguous float64 device tensors")
+    n = st.n
+    logL = logL if logL is not None else torch.empty(n, dtype=torch.float64, device=f.device)
+    status = status if status is not None else torch.empty(n, dtype=torch.int32, device=f.device)
+    d = _Desc()
+    d.n_bins = int(f.numel())
+    d.f, d.nk, d.D, d.R = f.data_ptr(), nk.data_ptr(), D.data_ptr(), R.data_ptr()
+    d.Rfg = None if Rfg is None else Rfg.data_ptr()
+    d.f_knee = float(f_knee)
+    d.arm_length = float(arm_length)
+    d.n_spl = int(n_spl)
+    flat = [int(v) for row in route for v in row]
+    for i in range(12):
+        d.route[i] = flat[i]
+    d.k_max = int(k_max)
+    c = st._c()
+    _check(lib().lps_loglike_plain_fp64_noalloc(ctypes.byref(d), ctypes.byref(c), _ptr(logL), _ptr(status),
+                                                _stream(stream)), "lps_loglike_plain_fp64_noalloc")
+    return logL, status
 
 
 @dataclass

@@ -12,6 +12,8 @@
 // batched kernels are measured against.
 #include <math.h>
 
+#include <mutex>
+
 #include "lps_internal.hpp"
 #include "lps_spline.hpp"
 #include "lps_validate.hpp"
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
 __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
     int n_blocks, const double* __restrict__ part, int s, int n_states, int n_spl, int k_max, int n_params,
     const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
-    const double* __restrict__ kx, const double* __restrict__ ky, double x_first, double x_last,
+    const double* __restrict__ kx, const double* __restrict__ ky, const double* __restrict__ f, int K,
     double* __restrict__ logL,
     uint32_t* __restrict__ status) {
   __shared__ double red[kPlainBlock];
@@ -112,6 +114,8 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    // band edges for the coverage test: log10 of the first and last bin
+    const double x_first = log10(f[0]), x_last = log10(f[K - 1]);
     uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kcnt, kx, ky, x_first, x_last);
     const double v = -red[0];
     if (st == 0 && !isfinite(v)) st |= LPS_ST_PSD;
@@ -120,27 +124,118 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
   }
 }
 
-}  // namespace
-
-hipError_t launch_plain(lps_ctx* ctx, const lps_states* st, double* logL, uint32_t* status, hipStream_t s) {
-  const int n = st->n_states;
-  const int K = ctx->n_bins;
-  const int nb = ctx->plain_blocks;
+// Every input of the plain path: the dataset arrays and its constants.
+struct PlainData {
+  int K, n_spl, k_max, n_params;
+  const double *f, *nk, *D, *R, *Rfg;
+  double L, f_knee;
   Route route;
-  for (int t = 0; t < 4; ++t)
-    for (int c = 0; c < 3; ++c) route.r[t][c] = ctx->route[t][c];
-  timing_begin(ctx, s);
+};
+
+// One bins launch and one finish launch per state, in state order on one
+// stream: part[0 .. ceil(K / kPlainBlock)) holds one state's block sums at a
+// time, each entry written by the bins launch before the finish launch reads it.
+hipError_t launch_plain_core(const PlainData& d, const lps_states* st, double* part, double* logL,
+                             uint32_t* status, hipStream_t s) {
+  const int n = st->n_states;
+  const int nb = (d.K + kPlainBlock - 1) / kPlainBlock;
   for (int i = 0; i < n; ++i) {
-    hipLaunchKernelGGL(k_plain_bins, dim3(nb), dim3(kPlainBlock), 0, s, K, ctx->f, ctx->nk, ctx->D, ctx->R,
-                       ctx->Rfg, ctx->arm_length, ctx->f_knee, ctx->n_spl, ctx->k_max, route, n, ctx->n_params, i,
-                       st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->plain_part);
-    hipLaunchKernelGGL(k_plain_finish, dim3(1), dim3(kPlainBlock), 0, s, nb, ctx->plain_part, i, n, ctx->n_spl,
-                       ctx->k_max, ctx->n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
-                       ctx->x_first,
-                       ctx->x_last, logL, status);
+    hipLaunchKernelGGL(k_plain_bins, dim3(nb), dim3(kPlainBlock), 0, s, d.K, d.f, d.nk, d.D, d.R, d.Rfg, d.L,
+                       d.f_knee, d.n_spl, d.k_max, d.route, n, d.n_params, i, st->params, st->knot_off,
+                       st->knot_cnt, st->knot_x, st->knot_y, part);
+    hipLaunchKernelGGL(k_plain_finish, dim3(1), dim3(kPlainBlock), 0, s, nb, part, i, n, d.n_spl, d.k_max,
+                       d.n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, d.f, d.K, logL,
+                       status);
   }
-  timing_end(ctx, s);
   return hipGetLastError();
 }
 
+// Scratch of the allocation-free entry point: the per-block sums of one state
+// (one double per kPlainBlock bins), 512 KiB, so at most 2^24 bins.  Each GPU
+// holds its own copy for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr int kNoallocBlocks = 1 << 16;
+static __device__ __align__(256) double scratch[kNoallocBlocks];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_plain(lps_ctx* ctx, const lps_states* st, double* logL, uint32_t* status, hipStream_t s) {
+  PlainData d;
+  d.K = ctx->n_bins;
+  d.n_spl = ctx->n_spl;
+  d.k_max = ctx->k_max;
+  d.n_params = ctx->n_params;
+  d.f = ctx->f;
+  d.nk = ctx->nk;
+  d.D = ctx->D;
+  d.R = ctx->R;
+  d.Rfg = ctx->Rfg;
+  d.L = ctx->arm_length;
+  d.f_knee = ctx->f_knee;
+  for (int t = 0; t < 4; ++t)
+    for (int c = 0; c < 3; ++c) d.route.r[t][c] = ctx->route[t][c];
+  timing_begin(ctx, s);
+  const hipError_t e = launch_plain_core(d, st, ctx->plain_part, logL, status, s);
+  timing_end(ctx, s);
+  return e;
+}
+
 }  // namespace lps
+
+extern "C" lps_status lps_loglike_plain_fp64_noalloc(const lps_dataset_desc* d, const lps_states* st,
+                                                     double* logL, uint32_t* status, void* stream) {
+  if (!d || !st) return LPS_E_NULL;
+  if (!d->f || !d->nk || !d->D || !d->R) return LPS_E_NULL;
+  if (d->n_bins < 1 || d->n_spl < 0 || d->n_spl > 4) return LPS_E_SHAPE;
+  if ((d->n_bins + lps::kPlainBlock - 1) / lps::kPlainBlock > lps::kNoallocBlocks) return LPS_E_CAPACITY;
+  if (d->k_max < 2 || d->k_max > lps::kMaxKnots) return LPS_E_CAPACITY;
+  if (!(d->f_knee > 0.0) || !(d->arm_length > 0.0)) return LPS_E_SHAPE;
+  for (int t = 0; t < 4; ++t)
+    for (int c = 0; c < 3; ++c) {
+      const int j = d->route[t][c];
+      if (j < -1 || j >= d->n_spl || (t == LPS_TERM_FG && j != -1)) return LPS_E_ROUTING;
+    }
+  if (st->n_states < 0) return LPS_E_SHAPE;
+  if (st->n_states == 0) return LPS_OK;
+  if (!st->params || !st->knot_off || !logL) return LPS_E_NULL;
+  if (d->n_spl > 0 && (!st->knot_x || !st->knot_y)) return LPS_E_NULL;
+  double* part = nullptr;
+  hipError_t e = lps::scratch_address(&part);
+  if (e != hipSuccess) return lps::device_status(e);
+  lps::PlainData pd;
+  pd.K = d->n_bins;
+  pd.n_spl = d->n_spl;
+  pd.k_max = d->k_max;
+  pd.n_params = d->Rfg ? 5 : 4;
+  pd.f = d->f;
+  pd.nk = d->nk;
+  pd.D = d->D;
+  pd.R = d->R;
+  pd.Rfg = d->Rfg;
+  pd.L = d->arm_length;
+  pd.f_knee = d->f_knee;
+  for (int t = 0; t < 4; ++t)
+    for (int c = 0; c < 3; ++c) pd.route.r[t][c] = d->route[t][c];
+  return lps::device_status(lps::launch_plain_core(pd, st, part, logL, status, (hipStream_t)stream));
+}
