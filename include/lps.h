@@ -66,7 +66,7 @@ typedef enum {
 typedef enum { LPS_FP64 = 0, LPS_MIXED = 1 } lps_precision;
 
 /* Per-state status bits (0 = valid). */
-#define LPS_ST_COUNT 1u       /* a spline has 1 knot, more than k_max knots, or bad offsets */
+#define LPS_ST_COUNT 1u       /* a spline has 1 knot, more than k_max knots, or offsets outside the knot arrays */
 #define LPS_ST_ORDER 2u       /* knot abscissae not strictly increasing */
 #define LPS_ST_COVER 4u       /* the edge knots do not enclose every bin */
 #define LPS_ST_NONFINITE 8u   /* a parameter or knot value is not finite */
@@ -120,6 +120,9 @@ typedef struct {
                                 (= s*n_spl+j) owns knot_cnt[i] knots starting at knot_off[i],
                                 so slots may have spare capacity (used by the sampler to
                                 edit knots in place); knot_off then needs n_states*n_spl entries. */
+  int64_t n_knots;           /* entries of knot_x and knot_y (>= 0).  A spline whose range
+                                [start, start + count) does not lie inside [0, n_knots) marks
+                                its state LPS_ST_COUNT and none of its knots is read. */
 } lps_states;
 
 /*
@@ -324,11 +327,26 @@ lps_status lps_dic(const double* logL, int32_t n_rec, int32_t n_temps, int32_t n
  * channels A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3.
  * P[n_ch][n_t/2 + 1] (device) receives c_k dt |X_k|^2 / (n_t mean(w^2)) at
  * f_k = k / (n_t dt), c_k = 1 at k = 0 and k = n_t/2 (n_t even), else 2, with X
- * the discrete Fourier transform (hipFFT, double).  Allocates temporary device
- * memory and a transform plan and synchronises `stream`: not for graph capture.
+ * the discrete Fourier transform (hipFFT, double).  A one-off call: it plans,
+ * allocates temporaries, synchronises `stream` and frees them (not for graph
+ * capture; repeated calls use lps_data_create / lps_data_periodogram_planned).
  */
 lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, double dt, const double* window,
                                 int32_t xyz_to_aet, double* P, void* stream);
+
+/* A planned periodogram for n_ch series of n_t samples on `device`: the hipFFT
+ * plan, its work area and the temporaries are allocated once here (synchronises;
+ * not during a capture), so that lps_data_periodogram_planned allocates nothing. */
+typedef struct lps_data_ctx lps_data_ctx;
+lps_status lps_data_create(int32_t n_ch, int32_t n_t, int device, lps_data_ctx** out /*[host]*/);
+/* Free a planned periodogram (NULL is a no-op); synchronises, not during a capture. */
+lps_status lps_data_destroy(lps_data_ctx* ctx);
+/* lps_data_periodogram on a planned context (the same arguments and output):
+ * asynchronous on `stream`, no allocation and no synchronisation, so it may be
+ * captured into a HIP graph.  One call at a time per context (the temporaries
+ * are shared). */
+lps_status lps_data_periodogram_planned(lps_data_ctx* ctx, const double* x, double dt, const double* window,
+                                        int32_t xyz_to_aet, double* P, void* stream);
 
 /* Averaged periodogram (Sec. "MCMC setup"): n_seg segments of seg_len consecutive
  * non-overlapping bins starting at bin k0 of P[n_ch][n_f] with frequencies f[n_f]

@@ -62,7 +62,8 @@ class _SamplerDesc(ctypes.Structure):
 
 class _States(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_int32), ("params", ctypes.c_void_p), ("knot_off", ctypes.c_void_p),
-                ("knot_x", ctypes.c_void_p), ("knot_y", ctypes.c_void_p), ("knot_cnt", ctypes.c_void_p)]
+                ("knot_x", ctypes.c_void_p), ("knot_y", ctypes.c_void_p), ("knot_cnt", ctypes.c_void_p),
+                ("n_knots", ctypes.c_int64)]
 
 
 SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
@@ -73,7 +74,8 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_stepping_stone", "lps_dic",
            "lps_data_periodogram", "lps_data_average", "lps_data_response",
            "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch", "lps_cov_build",
-           "lps_math64_check", "lps_loglike_plain_fp64_noalloc"]
+           "lps_math64_check", "lps_loglike_plain_fp64_noalloc",
+           "lps_data_create", "lps_data_destroy", "lps_data_periodogram_planned"]
 
 _lib = None
 
@@ -131,11 +133,15 @@ def lib():
     L.lps_cov_build.argtypes = [vp, ctypes.POINTER(_States), i32, i32, vp, vp, vp]
     L.lps_math64_check.argtypes = [vp, i32, i32, vp, vp]
     L.lps_loglike_plain_fp64_noalloc.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_States), vp, vp, vp]
+    L.lps_data_create.argtypes = [i32, i32, ctypes.c_int, ctypes.POINTER(vp)]
+    L.lps_data_destroy.argtypes = [vp]
+    L.lps_data_periodogram_planned.argtypes = [vp, vp, ctypes.c_double, vp, i32, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
                  "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response",
                  "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch",
-                 "lps_cov_build", "lps_math64_check", "lps_loglike_plain_fp64_noalloc"]:
+                 "lps_cov_build", "lps_math64_check", "lps_loglike_plain_fp64_noalloc", "lps_data_create",
+                 "lps_data_destroy", "lps_data_periodogram_planned"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -246,7 +252,8 @@ class States:
 
     def _c(self):
         return _States(self.n, self.params.data_ptr(), self.knot_off.data_ptr(), self.knot_x.data_ptr(),
-                       self.knot_y.data_ptr(), None if self.knot_cnt is None else self.knot_cnt.data_ptr())
+                       self.knot_y.data_ptr(), None if self.knot_cnt is None else self.knot_cnt.data_ptr(),
+                       int(min(self.knot_x.numel(), self.knot_y.numel())))
 
 
 class Context:
@@ -299,8 +306,12 @@ class Context:
     # ------------------------------------------------------------------
     def states(self, params, knot_off, knot_x, knot_y) -> States:
         dev = self.device
-        return States(_dev(params, torch.float64, dev), _dev(knot_off, torch.int32, dev),
-                      _dev(knot_x, torch.float64, dev), _dev(knot_y, torch.float64, dev))
+        kx, ky = _dev(knot_x, torch.float64, dev), _dev(knot_y, torch.float64, dev)
+        if kx.numel() == 0:
+            # a batch whose splines are all disabled holds no knots; the ABI still
+            # wants non-NULL arrays (the offsets decide what is read: nothing)
+            kx, ky = torch.zeros(1, dtype=torch.float64, device=dev), torch.zeros(1, dtype=torch.float64, device=dev)
+        return States(_dev(params, torch.float64, dev), _dev(knot_off, torch.int32, dev), kx, ky)
 
     def psd_build(self, st: States, k0=0, k1=None, parts=False, stream=None):
         k1 = self.n_bins if k1 is None else int(k1)
@@ -430,8 +441,12 @@ class CovContext:
 
     def states(self, params, knot_off, knot_x, knot_y) -> States:
         dev = self.device
-        return States(_dev(params, torch.float64, dev), _dev(knot_off, torch.int32, dev),
-                      _dev(knot_x, torch.float64, dev), _dev(knot_y, torch.float64, dev))
+        kx, ky = _dev(knot_x, torch.float64, dev), _dev(knot_y, torch.float64, dev)
+        if kx.numel() == 0:
+            # a batch whose splines are all disabled holds no knots; the ABI still
+            # wants non-NULL arrays (the offsets decide what is read: nothing)
+            kx, ky = torch.zeros(1, dtype=torch.float64, device=dev), torch.zeros(1, dtype=torch.float64, device=dev)
+        return States(_dev(params, torch.float64, dev), _dev(knot_off, torch.int32, dev), kx, ky)
 
     def loglike_batch(self, st: States, out=None, status=None, stream=None):
         n = st.n
@@ -512,6 +527,44 @@ def data_periodogram(x: torch.Tensor, dt, window=None, xyz_to_aet=False, stream=
                                       _ptr(P), _stream(stream)), "lps_data_periodogram")
     f = torch.arange(nf, dtype=torch.float64, device=xs.device) / (n_t * float(dt))
     return f, P
+
+
+class DataPlan:
+    """A planned periodogram of n_ch series of n_t samples (wraps lps_data_create /
+    lps_data_destroy): the transform plan and temporaries are made once, so that
+    periodogram() is asynchronous, allocates nothing on the device itself and may
+    be captured into a HIP graph."""
+
+    def __init__(self, n_ch, n_t, device=None):
+        _drain()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.n_ch, self.n_t = int(n_ch), int(n_t)
+        h = ctypes.c_void_p()
+        idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        _check(lib().lps_data_create(self.n_ch, self.n_t, idx, ctypes.byref(h)), "lps_data_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _release("lps_data_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def periodogram(self, x: torch.Tensor, dt, window=None, xyz_to_aet=False, out=None, stream=None):
+        """P [n_ch, n_t//2 + 1] of device series x [n_ch, n_t] (contiguous FP64); out, if
+        given, must be a contiguous FP64 tensor of that shape on the same device."""
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and tuple(x.shape) == (self.n_ch, self.n_t)
+        assert window is None or (window.is_cuda and window.dtype == torch.float64 and window.is_contiguous())
+        nf = self.n_t // 2 + 1
+        P = out if out is not None else torch.empty((self.n_ch, nf), dtype=torch.float64, device=x.device)
+        _check(lib().lps_data_periodogram_planned(self._h, _ptr(x), float(dt), _ptr(window), 1 if xyz_to_aet else 0,
+                                                  _ptr(P), _stream(stream)), "lps_data_periodogram_planned")
+        return P
 
 
 def data_average(f: torch.Tensor, P: torch.Tensor, k0, seg_len, n_seg, stream=None):

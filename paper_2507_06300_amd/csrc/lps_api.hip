@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "lps_internal.hpp"
@@ -105,7 +106,7 @@ void free_ctx(lps_ctx* c) {
 
 lps_status check_states(const lps_ctx* ctx, const lps_states* st) {
   if (!ctx || !st) return LPS_E_NULL;
-  if (st->n_states < 0) return LPS_E_SHAPE;
+  if (st->n_states < 0 || st->n_knots < 0) return LPS_E_SHAPE;
   if (st->n_states > ctx->max_states) return LPS_E_CAPACITY;
   if (st->n_states == 0) return LPS_OK;
   if (!st->params || !st->knot_off) return LPS_E_NULL;
@@ -152,6 +153,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   const int K = d->n_bins;
   // A and E can be merged when their response (and foreground) rows agree bitwise.
   bool ae_equal = true;
+  double nk_uniform = 0.0;
   {
     std::vector<double> h(2 * (size_t)K);
     const double* tabs[2] = {d->R, d->Rfg};
@@ -166,6 +168,13 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
       return LPS_E_DEVICE;
     for (int k = 0; k < K; ++k)
       if (!(fh[k] > 0.0) || (k > 0 && !(fh[k] > fh[k - 1]))) return LPS_E_SHAPE;
+    if (hipMemcpy(fh.data(), d->nk, (size_t)K * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return LPS_E_DEVICE;
+    nk_uniform = fh[0];
+    for (int k = 0; k < K; ++k) {
+      if (!(fh[k] >= 1.0) || !std::isfinite(fh[k])) return LPS_E_SHAPE;   // N_k >= 1
+      if (fh[k] != fh[0]) nk_uniform = 0.0;
+    }
   }
   Layout L;
   lps_status rs = classify(d, ae_equal, &L);
@@ -189,6 +198,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   c->arm_length = d->arm_length;
   c->lay = L;
   c->plain_blocks = (K + lps::kPlainBlock - 1) / lps::kPlainBlock;
+  c->nk_uniform = nk_uniform;
 
   const size_t S = (size_t)d->max_states;
   const size_t G = (size_t)L.n_grp;

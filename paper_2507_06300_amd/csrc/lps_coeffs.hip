@@ -21,7 +21,7 @@ namespace {
 // lane builds one piece of every exponent group.
 __global__ __launch_bounds__(256) void k_coeffs(int n_states, int n_spl, int k_max, Layout lay, int n_params,
                                                 const double* __restrict__ params, const int32_t* __restrict__ off,
-                                                const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
+                                                const int32_t* __restrict__ kcnt, int64_t n_knots, const double* __restrict__ kx,
                                                 const double* __restrict__ ky, double x_first, double x_last,
                                                 double x_knee, double* __restrict__ bx, double* __restrict__ coef64,
                                                 float* __restrict__ coef32, int32_t* __restrict__ n_int,
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_coeffs(int n_states, int n_spl, int k_m
   if (s >= n_states) return;
   const int G = lay.n_grp;
   const uint32_t st =
-      validate_state_wave(lane, s, n_states, n_spl, k_max, n_params, params, off, kcnt, kx, ky, x_first, x_last);
+      validate_state_wave(lane, s, n_states, n_spl, k_max, n_params, params, off, kcnt, n_knots, kx, ky, x_first, x_last);
   if (lane == 0) status_ws[s] = st;
   if (st) {
     if (lane < G) n_int[s * G + lane] = 0;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_coeffs(int n_states, int n_spl, int k_m
     const int j = lay.grp_spline[g];
     const size_t base = (size_t)(s * G + g) * kMaxKnots;
     int cnt = 0, a0 = 0;
-    if (j >= 0) knot_range(off, kcnt, s * n_spl + j, a0, cnt);
+    if (j >= 0) knot_range(off, kcnt, s * n_spl + j, n_knots, a0, cnt);
     const int n_pieces = cnt == 0 ? 1 : cnt - 1;
     if (lane == 0) n_int[s * G + g] = n_pieces;
     if (lane >= n_pieces) continue;
@@ -104,7 +104,7 @@ hipError_t launch_coeffs(lps_ctx* ctx, const lps_states* st, hipStream_t s) {
   const int n = st->n_states;
   const int waves = 4;
   hipLaunchKernelGGL(k_coeffs, dim3((n + waves - 1) / waves), dim3(waves * kWave), 0, s, n, ctx->n_spl, ctx->k_max, ctx->lay,
-                     ctx->n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, ctx->x_first,
+                     ctx->n_params, st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y, ctx->x_first,
                      ctx->x_last,
                      log10(ctx->f_knee), ctx->bx, ctx->coef64, ctx->coef32, ctx->n_int, ctx->scal, ctx->status_ws,
                      ctx->wide_count);

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_cov_c0(int K, const double* __restrict_
 // One wave per state: validation (every spline slot), then one lane per piece.
 __global__ __launch_bounds__(256) void k_cov_coeffs(int n_states, int n_spl, int k_max, int n_params,
                                                     const double* __restrict__ params, const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
+                                                    const int32_t* __restrict__ kcnt, int64_t n_knots, const double* __restrict__ kx,
                                                     const double* __restrict__ ky, double x_first, double x_last,
                                                     double* __restrict__ bx, double* __restrict__ coef,
                                                     int32_t* __restrict__ npc, uint32_t* __restrict__ status) {
@@ -132,11 +132,11 @@ __global__ __launch_bounds__(256) void k_cov_coeffs(int n_states, int n_spl, int
   const int s = uniform(blockIdx.x * (blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (s >= n_states) return;
   const uint32_t st =
-      validate_state_wave(lane, s, n_states, n_spl, k_max, n_params, params, off, kcnt, kx, ky, x_first, x_last);
+      validate_state_wave(lane, s, n_states, n_spl, k_max, n_params, params, off, kcnt, n_knots, kx, ky, x_first, x_last);
   if (lane == 0) status[s] = st;
   for (int j = 0; j < kCovMaxSpl; ++j) {
     int a = 0, n = 0;
-    if (j < n_spl && st == 0) knot_range(off, kcnt, s * n_spl + j, a, n);
+    if (j < n_spl && st == 0) knot_range(off, kcnt, s * n_spl + j, n_knots, a, n);
     const int np = n >= 2 ? n - 1 : 0;
     const size_t row = (size_t)s * kCovMaxSpl + j;
     if (lane == 0) npc[row] = np;
@@ -353,7 +353,7 @@ namespace covk {
 
 lps_status check_cov_states(const lps_cov_ctx* ctx, const lps_states* st) {
   if (!ctx || !st) return LPS_E_NULL;
-  if (st->n_states < 0) return LPS_E_SHAPE;
+  if (st->n_states < 0 || st->n_knots < 0) return LPS_E_SHAPE;
   if (st->n_states > ctx->max_states) return LPS_E_CAPACITY;
   if (st->n_states == 0) return LPS_OK;
   if (!st->params || !st->knot_off) return LPS_E_NULL;
@@ -364,7 +364,7 @@ lps_status check_cov_states(const lps_cov_ctx* ctx, const lps_states* st) {
 hipError_t launch_cov_coeffs(lps_cov_ctx* c, const lps_states* st, hipStream_t s) {
   const int n = st->n_states;
   hipLaunchKernelGGL(k_cov_coeffs, dim3((n + 3) / 4), dim3(256), 0, s, n, c->n_spl, c->k_max, c->n_params,
-                     st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, c->x_first, c->x_last, c->bx,
+                     st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y, c->x_first, c->x_last, c->bx,
                      c->coef, c->npc, c->status);
   return hipGetLastError();
 }

@@ -60,7 +60,7 @@ __device__ inline void mo_add(double* __restrict__ m, const double (&v)[4]) {
 }
 
 __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict__ mo_ws,
-                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, int64_t n_knots,
                                                   const double* __restrict__ kx, const double* __restrict__ ky,
                                                   int n_params, const double* __restrict__ c0,
                                                   double* __restrict__ logL, double* __restrict__ dparams,
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
     if (lane < n_params) dparams[lane * (size_t)A.n_states + s] = 0.0;
     for (int j = 0; j < n_spl; ++j) {
       int a, cn;
-      knot_range(off, kcnt, s * n_spl + j, a, cn);
+      knot_range(off, kcnt, s * n_spl + j, n_knots, a, cn);
       if (a < 0) continue;
       for (int i = lane; i < cn; i += kWave) {
         dkx[a + i] = 0.0;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
   BackLds& B = *reinterpret_cast<BackLds*>(&L.val[0][0][0]);
   for (int j = 0; j < n_spl; ++j) {
     int a, n;
-    knot_range(off, kcnt, s * n_spl + j, a, n);
+    knot_range(off, kcnt, s * n_spl + j, n_knots, a, n);
     if (n == 0) continue;
     double M[4] = {0.0, 0.0, 0.0, 0.0};
     if (lane + 1 < n)
@@ -395,7 +395,7 @@ lps_status lps_cov_loglike_grad_batch(lps_cov_ctx* c, const lps_states* st, doub
   hipError_t e = launch_cov_coeffs(c, st, s);
   if (e != hipSuccess) return device_status(e);
   const CovArgs A = cov_args(c, st);
-  hipLaunchKernelGGL(k_cov_grad, dim3((n + 3) / 4), dim3(256), 0, s, A, c->gmo, st->knot_off, st->knot_cnt, st->knot_x,
+  hipLaunchKernelGGL(k_cov_grad, dim3((n + 3) / 4), dim3(256), 0, s, A, c->gmo, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x,
                      st->knot_y, c->n_params, c->c0, logL, dparams, dknot_x, dknot_y, status);
   return device_status(hipGetLastError());
 }

@@ -132,53 +132,135 @@ inline dim3 blocks_for(long n, int tpb) { return dim3((unsigned)((n + tpb - 1) /
 }  // namespace
 }  // namespace lps
 
+// A planned periodogram: the transform plan, its work area and the
+// temporaries, all made once so that every periodogram call is asynchronous
+// and allocates nothing.
+struct lps_data_ctx {
+  int device;
+  int n_ch, n_t, nf;
+  hipfftHandle plan;
+  bool have_plan;
+  void* work;                  // transform work area (owned)
+  double* xw;                  // [n_ch][n_t] windowed (and combined) series
+  hipfftDoubleComplex* X;      // [n_ch][nf] transforms
+  double* w2;                  // [1 + kWinParts]: mean(w^2), then the partial sums
+};
+
+namespace {
+
+void free_data_ctx(lps_data_ctx* c) {
+  if (c->have_plan) (void)hipfftDestroy(c->plan);
+  void* ptrs[] = {c->work, c->xw, c->X, c->w2};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+lps_status periodogram_on(lps_data_ctx* c, const double* x, double dt, const double* window, int32_t xyz_to_aet,
+                          double* P, hipStream_t s) {
+  const int n_ch = c->n_ch, n_t = c->n_t, nf = c->nf;
+  if (hipfftSetStream(c->plan, s) != HIPFFT_SUCCESS) return LPS_E_DEVICE;
+  hipLaunchKernelGGL(lps::k_prep_series, lps::blocks_for(n_t, 256), dim3(256), 0, s, n_ch, n_t, x, window,
+                     xyz_to_aet, c->xw);
+  hipLaunchKernelGGL(lps::k_window_part, dim3(lps::kWinParts), dim3(256), 0, s, n_t, window, c->w2 + 1);
+  hipLaunchKernelGGL(lps::k_window_power, dim3(1), dim3(lps::kWinParts), 0, s, n_t, window, c->w2 + 1, c->w2);
+  if (hipfftExecD2Z(c->plan, (hipfftDoubleReal*)c->xw, c->X) != HIPFFT_SUCCESS) return LPS_E_DEVICE;
+  hipLaunchKernelGGL(lps::k_power, lps::blocks_for((long)n_ch * nf, 256), dim3(256), 0, s, n_ch, n_t, nf, dt, c->X,
+                     c->w2, P);
+  return lps::device_status(hipGetLastError());
+}
+
+}  // namespace
+
 extern "C" {
+
+lps_status lps_data_create(int32_t n_ch, int32_t n_t, int device, lps_data_ctx** out) {
+  if (!out) return LPS_E_NULL;
+  *out = nullptr;
+  if (n_ch < 1 || n_t < 2) return LPS_E_SHAPE;
+  if (hipSetDevice(device) != hipSuccess) return LPS_E_DEVICE;
+  lps_data_ctx* c = new lps_data_ctx;
+  c->device = device;
+  c->n_ch = n_ch;
+  c->n_t = n_t;
+  c->nf = n_t / 2 + 1;
+  c->plan = 0;
+  c->have_plan = false;
+  c->work = nullptr;
+  c->xw = nullptr;
+  c->X = nullptr;
+  c->w2 = nullptr;
+  const int nf = c->nf;
+  bool ok = hipMalloc((void**)&c->xw, (size_t)n_ch * n_t * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->X, (size_t)n_ch * nf * sizeof(hipfftDoubleComplex)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->w2, (1 + lps::kWinParts) * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    free_data_ctx(c);
+    return LPS_E_NOMEM;
+  }
+  // batched real-to-complex plan with a caller-owned work area
+  int n[1] = {n_t};
+  int inembed[1] = {n_t}, onembed[1] = {nf};
+  size_t work = 0;
+  if (hipfftCreate(&c->plan) != HIPFFT_SUCCESS) {
+    free_data_ctx(c);
+    return LPS_E_DEVICE;
+  }
+  c->have_plan = true;
+  if (hipfftSetAutoAllocation(c->plan, 0) != HIPFFT_SUCCESS ||
+      hipfftMakePlanMany(c->plan, 1, n, inembed, 1, n_t, onembed, 1, nf, HIPFFT_D2Z, n_ch, &work) !=
+          HIPFFT_SUCCESS) {
+    free_data_ctx(c);
+    return LPS_E_DEVICE;
+  }
+  if (work > 0) {
+    if (hipMalloc(&c->work, work) != hipSuccess) {
+      free_data_ctx(c);
+      return LPS_E_NOMEM;
+    }
+    if (hipfftSetWorkArea(c->plan, c->work) != HIPFFT_SUCCESS) {
+      free_data_ctx(c);
+      return LPS_E_DEVICE;
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    free_data_ctx(c);
+    return LPS_E_DEVICE;
+  }
+  *out = c;
+  return LPS_OK;
+}
+
+lps_status lps_data_destroy(lps_data_ctx* ctx) {
+  if (!ctx) return LPS_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_data_ctx(ctx);
+  return LPS_OK;
+}
+
+lps_status lps_data_periodogram_planned(lps_data_ctx* ctx, const double* x, double dt, const double* window,
+                                        int32_t xyz_to_aet, double* P, void* stream) {
+  if (!ctx || !x || !P) return LPS_E_NULL;
+  if (!(dt > 0.0) || (xyz_to_aet && ctx->n_ch != 3)) return LPS_E_SHAPE;
+  return periodogram_on(ctx, x, dt, window, xyz_to_aet, P, (hipStream_t)stream);
+}
 
 lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, double dt, const double* window,
                                 int32_t xyz_to_aet, double* P, void* stream) {
   if (!x || !P) return LPS_E_NULL;
   if (n_ch < 1 || n_t < 2 || !(dt > 0.0) || (xyz_to_aet && n_ch != 3)) return LPS_E_SHAPE;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return LPS_E_DEVICE;
+  lps_data_ctx* c = nullptr;
+  lps_status st = lps_data_create(n_ch, n_t, device, &c);
+  if (st != LPS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const int nf = n_t / 2 + 1;
-  double* xw = nullptr;
-  double* w2 = nullptr;
-  hipfftDoubleComplex* X = nullptr;
-  hipfftHandle plan = 0;
-  bool have_plan = false;
-  hipError_t e = hipMalloc((void**)&xw, (size_t)n_ch * n_t * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&X, (size_t)n_ch * nf * sizeof(hipfftDoubleComplex));
-  if (e == hipSuccess) e = hipMalloc((void**)&w2, (1 + lps::kWinParts) * sizeof(double));   // mean, partials
-  lps_status st = LPS_OK;
-  if (e != hipSuccess) st = LPS_E_NOMEM;
-  if (st == LPS_OK) {
-    int n[1] = {n_t};
-    int inembed[1] = {n_t}, onembed[1] = {nf};
-    if (hipfftPlanMany(&plan, 1, n, inembed, 1, n_t, onembed, 1, nf, HIPFFT_D2Z, n_ch) != HIPFFT_SUCCESS ||
-        hipfftSetStream(plan, s) != HIPFFT_SUCCESS) {
-      st = LPS_E_DEVICE;
-    } else {
-      have_plan = true;
-    }
-  }
-  if (st == LPS_OK) {
-    hipLaunchKernelGGL(lps::k_prep_series, lps::blocks_for(n_t, 256), dim3(256), 0, s, n_ch, n_t, x, window,
-                       xyz_to_aet, xw);
-    hipLaunchKernelGGL(lps::k_window_part, dim3(lps::kWinParts), dim3(256), 0, s, n_t, window, w2 + 1);
-    hipLaunchKernelGGL(lps::k_window_power, dim3(1), dim3(lps::kWinParts), 0, s, n_t, window, w2 + 1, w2);
-    if (hipfftExecD2Z(plan, (hipfftDoubleReal*)xw, X) != HIPFFT_SUCCESS) st = LPS_E_DEVICE;
-  }
-  if (st == LPS_OK) {
-    hipLaunchKernelGGL(lps::k_power, lps::blocks_for((long)n_ch * nf, 256), dim3(256), 0, s, n_ch, n_t, nf, dt, X,
-                       w2, P);
-    st = lps::device_status(hipGetLastError());
-  }
+  st = periodogram_on(c, x, dt, window, xyz_to_aet, P, s);
   // the temporaries are released after the stream has consumed them
   const hipError_t sync = hipStreamSynchronize(s);
   if (st == LPS_OK && sync != hipSuccess) st = lps::device_status(sync);
-  if (have_plan) (void)hipfftDestroy(plan);
-  if (xw) (void)hipFree(xw);
-  if (X) (void)hipFree(X);
-  if (w2) (void)hipFree(w2);
+  free_data_ctx(c);
   return st;
 }
 

@@ -132,9 +132,9 @@ __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int 
   }
 }
 
-template <typename R, int MODE, int NCH, bool FG, int B>
+template <typename R, int MODE, int NCH, bool FG, int B, int M, bool UNI>
 __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int n_tiles, int tile, int K,
-                                                 int k_pad, int ref_chunk, const R* __restrict__ tab,
+                                                 int k_pad, int ref_chunk, R nl_uni, const R* __restrict__ tab,
                                                  const double* __restrict__ x64, const double* __restrict__ bx,
                                                  const R* __restrict__ coef, const double* __restrict__ coef64,
                                                  uint32_t* __restrict__ wide_count, int2* __restrict__ wide_list,
@@ -185,8 +185,9 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   const int s_end = min(s_begin + tile, n_states);
   const int kbase = chunk * CH;
 
-  // per-bin rows for this lane's B bins (lane-strided, coalesced)
-  R xr[B], NL[B];
+  // per-bin rows for this lane's B bins (lane-strided, coalesced); with a
+  // uniform N_k the log weight is the scalar nl_uni and needs no row
+  R xr[B], NL[UNI ? 1 : B];
   R Kt[NT][NCH][B];
   R ND[NCH][B];
 #pragma unroll
@@ -199,8 +200,10 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       for (int c = 0; c < NCH; ++c) Kt[term][c][b] = tab[(size_t)tab_k(term, c, NCH) * k_pad + k];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) ND[c][b] = tab[(size_t)tab_nd(c, NT, NCH) * k_pad + k];
-    NL[b] = tab[(size_t)tab_nl(NT, NCH) * k_pad + k];
+    if constexpr (!UNI) NL[b] = tab[(size_t)tab_nl(NT, NCH) * k_pad + k];
   }
+  // bins of this chunk past the last one (the padded tail of the final chunk)
+  const bool tail = kbase + CH > K;
   const int klast = min(kbase + CH, K) - 1;
   const double xf = x64[kbase];
   const double xl = x64[klast];
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
           const int pl = q * G + g;
           const bool str = (straddle >> pl) & 1ull;
           const bool mul = (multi >> pl) & 1ull;
-          R Q[B];
+          R Q[B] = {};
           if (mul) {   // several breakpoints inside the chunk: each piece from memory, select per bin
             const int i0 = __builtin_amdgcn_readlane(pi0, pl);
             const int i1 = __builtin_amdgcn_readlane(pi1, pl);
@@ -385,54 +388,135 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
           fold(g, E);
         }
       }
-      // One reciprocal and one logarithm per bin for all channels,
-      //   sum_c ND_c / S_c = num / prod_c S_c,   sum_c w_c ln S_c = ln2 log2(prod_c S_c^w_c)
-      // (w = 2 for the merged A/E row), accumulated along the lane's bins.
+      // Per bin, all channels at once:
+      //   sum_c ND_c / S_c = num / P,  P = prod_c S_c,
+      //   sum_c w_c ln S_c = ln2 log2 L,  L = prod_c S_c^w_c  (w = 2 for the merged A/E row).
+      // Groups of M consecutive bins of the lane then share one reciprocal,
+      //   num_a / P_a + num_b / P_b = (num_a P_b + num_b P_a) / (P_a P_b),
+      // and, when every bin carries the same N_k, one logarithm,
+      //   N ln2 (log2 L_a + log2 L_b) = N ln2 log2 (L_a L_b).
+      // A lane whose group products are not normal numbers (an extreme state
+      // left the single-precision range) takes the per-channel path below.
+      // L = P S0 (merged A/E) or P (three channels): a group's product of L is
+      // the product of P times, for the merged rows, the product of S0.
       R v = 0;
+      R Pm[B], Nm[B], Lm[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         if constexpr (NCH == 2) {
-          const R P = S[0][b] * S[1][b];
-          const R num = ND[1][b] * S[0][b] + ND[0][b] * S[1][b];
-          v += num * Math<R>::rcp_(P);
-          v += NL[b] * Math<R>::log2_(P * S[0][b]);
+          Pm[b] = S[0][b] * S[1][b];
+          Nm[b] = ND[1][b] * S[0][b] + ND[0][b] * S[1][b];
+          Lm[b] = UNI ? S[0][b] : Pm[b] * S[0][b];
         } else {
           const R P01 = S[0][b] * S[1][b];
-          const R P = P01 * S[2][b];
-          const R num = S[2][b] * (ND[1][b] * S[0][b] + ND[0][b] * S[1][b]) + ND[2][b] * P01;
-          v += num * Math<R>::rcp_(P);
-          v += NL[b] * Math<R>::log2_(P);
+          Pm[b] = P01 * S[2][b];
+          Nm[b] = S[2][b] * (ND[1][b] * S[0][b] + ND[0][b] * S[1][b]) + ND[2][b] * P01;
+          Lm[b] = UNI ? (R)1 : Pm[b];
         }
       }
+      if constexpr (UNI) {
+        // padded bins of the final chunk: N = 0 there, so their log term is
+        // dropped (L = 1: P and S0 set to 1; their num is 0)
+        if (tail) {
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            const bool in = kbase + b * kWave + lane < K;
+            Lm[b] = in ? Lm[b] : (R)1;
+            Pm[b] = in ? Pm[b] : (R)1;
+          }
+        }
+      }
+#pragma unroll
+      for (int w = 1; w < M; w *= 2)
+#pragma unroll
+        for (int b = 0; b < B; b += 2 * w) {
+          Nm[b] = Nm[b] * Pm[b + w] + Nm[b + w] * Pm[b];
+          Pm[b] = Pm[b] * Pm[b + w];
+          if constexpr (UNI && NCH == 2) Lm[b] = Lm[b] * Lm[b + w];
+        }
+      if constexpr (UNI) {
+#pragma unroll
+        for (int b = 0; b < B; b += M) Lm[b] = NCH == 2 ? Pm[b] * Lm[b] : Pm[b];
+      }
+      bool ok = true;
+      // With a uniform N_k the lane's B bins need one logarithm: the group
+      // products are split into mantissa and exponent, the mantissas (in
+      // [1/2, 1)) multiplied and the exponents added exactly, so the hardware
+      // logarithm only sees an argument in [2^-(B/M), 1) and its error does not
+      // grow with the size of log2 L.
+      R mprod = 1;
+      int esum = 0;
+#pragma unroll
+      for (int b = 0; b < B; b += M) {
+        v += Nm[b] * Math<R>::rcp_(Pm[b]);
+        ok = ok && __builtin_isnormal(Pm[b]);
+        if constexpr (UNI) {
+          int e;
+          mprod *= frexp(Lm[b], &e);
+          esum += e;
+          ok = ok && __builtin_isnormal(Lm[b]);
+        }
+      }
+      if constexpr (UNI) {
+        v += nl_uni * (Math<R>::log2_(mprod) + (R)esum);
+      } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) v += NL[b] * Math<R>::log2_(Lm[b]);
+      }
       Acc acc = (Acc)v;
-      if (!isfinite(acc)) {
+      if (!ok || !isfinite(acc)) {
         // A channel product left the floating-point range (an extreme state):
         // redo the lane's bins with one reciprocal and logarithm per channel, so
         // that only a non-finite or vanishing channel PSD marks the state.
         R w = 0;
 #pragma unroll
-        for (int b = 0; b < B; ++b)
+        for (int b = 0; b < B; ++b) {
+          R nl;
+          if constexpr (UNI) nl = kbase + b * kWave + lane < K ? nl_uni : (R)0;
+          else nl = NL[b];
 #pragma unroll
           for (int c = 0; c < NCH; ++c) {
             const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;
-            w += ND[c][b] * Math<R>::rcp_(S[c][b]) + (lw * NL[b]) * Math<R>::log2_(S[c][b]);
+            int e;
+            const R m = frexp(S[c][b], &e);
+            w += ND[c][b] * Math<R>::rcp_(S[c][b]) + (lw * nl) * (Math<R>::log2_(m) + (R)e);
           }
+        }
         acc = (Acc)w;
       }
       red[wv][lane * SUB + q] = acc;
     }
-    // lane q adds the 64 lane partials of state sub + q in a fixed order (double)
+    // The 64 lane partials of each state are added in double by LP lanes, each
+    // taking a fixed run of them, and the LP sums are then added in lane order
+    // (lane LP q ends with the total of state sub + q): a fixed order throughout.
     wave_lds_sync();
-    if (lane < nsub) {
+    {
+      constexpr int LP = kWave / SUB;
+      constexpr int RUN = (kWave + LP - 1) / LP;
+      const int q = lane / LP, r = lane - q * LP;
+      const bool mine = q < nsub;
       double sum = 0.0;
-#pragma unroll 8
-      for (int i = 0; i < kWave; ++i) sum += (double)red[wv][i * SUB + lane];
-      partial[(size_t)(sub + lane) * n_chunks + chunk] = sum;
-      if (kMixed && !isfinite(sum)) {
-        // a channel PSD left the single-precision range (a wildly swinging
-        // spline): queue the (state, chunk) for the double-range pass
-        const unsigned slot = atomicAdd(wide_count, 1u);
-        if (slot < (unsigned)wide_cap) wide_list[slot] = make_int2(sub + lane, chunk);
+      if (mine) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < RUN; i += 2) {
+          const int i0 = r * RUN + i;
+          if (i0 < kWave && i < RUN) s0 += (double)red[wv][i0 * SUB + q];
+          if (i0 + 1 < kWave && i + 1 < RUN) s1 += (double)red[wv][(i0 + 1) * SUB + q];
+        }
+        sum = s0 + s1;
+      }
+      double tot = sum;
+#pragma unroll
+      for (int d = 1; d < LP; ++d) tot += __shfl_down(sum, d, kWave);
+      if (mine && r == 0) {
+        partial[(size_t)(sub + q) * n_chunks + chunk] = tot;
+        if (kMixed && !isfinite(tot)) {
+          // a channel PSD left the single-precision range (a wildly swinging
+          // spline): queue the (state, chunk) for the double-range pass
+          const unsigned slot = atomicAdd(wide_count, 1u);
+          if (slot < (unsigned)wide_cap) wide_list[slot] = make_int2(sub + q, chunk);
+        }
       }
     }
     wave_lds_sync();
@@ -459,17 +543,19 @@ __global__ __launch_bounds__(256) void k_finalize(int n_states, int n_chunks, co
   }
 }
 
-template <typename R, int B>
+template <typename R, int B, bool UNI>
 hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, const R* tab, const R* coef,
                     hipStream_t s) {
   const Layout& L = ctx->lay;
   const int items = n_chunks * n_tiles;
   dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
   const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
+  constexpr int M = kMergeBins < B ? kMergeBins : B;
+  const R nl_uni = (R)(ctx->nk_uniform * kLn2);
 #define LPS_FWD(MODE, NCH, FG)                                                                              \
-  hipLaunchKernelGGL((k_forward<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,     \
-                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->coef64, ctx->wide_count, \
-                     ctx->wide_list, ctx->wide_cap, ctx->n_int,                                               \
+  hipLaunchKernelGGL((k_forward<R, MODE, NCH, FG, B, M, UNI>), grid, block, 0, s, n, n_chunks, n_tiles, tile, \
+                     ctx->n_bins, k_pad, kChunk32, nl_uni, tab, ctx->x, ctx->bx, coef, ctx->coef64,           \
+                     ctx->wide_count, ctx->wide_list, ctx->wide_cap, ctx->n_int,                               \
                      ctx->scal,                                                                               \
                      ctx->partial)
   const bool fg = L.has_fg != 0;
@@ -543,16 +629,21 @@ hipError_t launch_forward(lps_ctx* ctx, const lps_states* st, lps_precision prec
   const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
   const int n_tiles = (n + sh.tile - 1) / sh.tile;
   timing_begin(ctx, s);
+  const bool uni = ctx->nk_uniform > 0.0;
   if (mixed) {
     if (sh.bins_per_lane == 4)
-      e = dispatch<float, 4>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s);
+      e = uni ? dispatch<float, 4, true>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s)
+              : dispatch<float, 4, false>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s);
     else
-      e = dispatch<float, 8>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s);
+      e = uni ? dispatch<float, 8, true>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s)
+              : dispatch<float, 8, false>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab32, ctx->coef32, s);
   } else {
     if (sh.bins_per_lane == 2)
-      e = dispatch<double, 2>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s);
+      e = uni ? dispatch<double, 2, true>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s)
+              : dispatch<double, 2, false>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s);
     else
-      e = dispatch<double, 4>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s);
+      e = uni ? dispatch<double, 4, true>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s)
+              : dispatch<double, 4, false>(ctx, n, n_chunks, n_tiles, sh.tile, ctx->tab64, ctx->coef64, s);
   }
   if (e != hipSuccess) return e;
   timing_end(ctx, s);

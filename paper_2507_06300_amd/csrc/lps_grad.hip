@@ -69,6 +69,174 @@ __device__ inline T reduce_scatter(const T (&v)[1 << M], T* __restrict__ buf, in
   return r;
 }
 
+// Elementary functions of the per-bin score.  WIDE = false: the working
+// precision of the adjoint (hardware single-precision functions, the logarithm
+// taken on the mantissa with the exponent added exactly; or the library's FP64
+// functions).  WIDE = true: the double-range redo of a single-precision lane
+// (exact exponent, single-precision accuracy).
+template <typename T, bool WIDE>
+struct ScoreMath;
+template <>
+struct ScoreMath<float, false> {
+  __device__ static inline float exp2(float q) { return __builtin_amdgcn_exp2f(q); }
+  __device__ static inline float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+  // the exponent exactly, the hardware logarithm on the mantissa in [1/2, 1)
+  // (its error is then a fixed absolute amount, not a fraction of log2 v)
+  __device__ static inline float log2(float v) {
+    int e;
+    const float m = frexpf(v, &e);
+    return __builtin_amdgcn_logf(m) + (float)e;
+  }
+};
+template <>
+struct ScoreMath<double, false> {
+  __device__ static inline double exp2(double q) { return exp2_d(q); }
+  __device__ static inline double rcp(double v) { return rcp_d(v); }
+  __device__ static inline double log2(double v) { return log2_d(v); }
+};
+template <>
+struct ScoreMath<double, true> {
+  // 2^q over the double range: the integer part exactly, the fraction in single precision
+  __device__ static inline double exp2(float q) {
+    const double qd = (double)q;
+    const double n = fmin(fmax(floor(qd), -2100.0), 2100.0);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(qd - n)), (int)n);
+  }
+  __device__ static inline double rcp(double v) { return 1.0 / v; }
+  __device__ static inline double log2(double v) {
+    int e = 0;
+    const double m = frexp(v, &e);
+    return (double)e + (double)__builtin_amdgcn_logf((float)m);
+  }
+};
+
+// Channel PSDs, logL term, score and group sensitivities of bin b from the
+// group exponents qx[g] = Q_g(x_b) (factors 2^Q).  Returns the bin's logL term
+// (in units of the table rows), adds the template sums of the shared and paper
+// layouts to v1 (OMS), v2 (TM) and the foreground sum to v3, and writes the
+// sensitivity dlogL/dQ_g / ln 2 of every group to gq.  T is the arithmetic
+// type: the working precision, or double for a lane whose single-precision
+// values left the range.
+template <typename T, bool WIDE, int MODE, int NCH, bool FG, int G, int NT, int B, typename R>
+__device__ inline T bin_score(int b, const R (&qx)[G], const R (&Kt)[NT][NCH][B], const R (&ND)[NCH][B], R nl,
+                              R w_oms, R w_tm, R e_fg, T& v1, T& v2, T& v3, T (&gq)[G]) {
+  using SM = ScoreMath<T, WIDE>;
+  T e[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) e[g] = SM::exp2(qx[g]);
+  T S[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) S[c] = FG ? (T)Kt[3][c][b] * (T)e_fg : (T)0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if constexpr (MODE == kSplit) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) S[c] += (T)Kt[g][c][b] * e[g];
+    } else if constexpr (MODE == kShared) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+        S[c] += (g == 0 ? ((T)w_oms * (T)Kt[0][c][b] + (T)w_tm * (T)Kt[1][c][b]) : (T)Kt[2][c][b]) * e[g];
+    } else {
+      if (g < 3) {
+        S[g] += ((T)w_oms * (T)Kt[0][g][b] + (T)w_tm * (T)Kt[1][g][b]) * e[g];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) S[c] += (T)Kt[2][c][b] * e[g];
+      }
+    }
+  }
+  const T Nn = (T)nl * (T)(1.0 / kLn2);
+  T h[NCH];
+  T l = 0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const T lw = (NCH == 2 && c == 0) ? (T)2 : (T)1;
+    const T r = SM::rcp(S[c]);
+    const T q1 = (T)ND[c][b] * r;
+    l += q1;
+    h[c] = (q1 - lw * Nn) * r;       // dlogL/dS~ (scaled units), A and E summed when merged
+  }
+  // sum_c w_c ln S_c = ln2 log2 prod_c S_c^w_c (w = 2 for the merged A/E row): one logarithm
+  const T Lp = NCH == 2 ? S[0] * S[0] * S[1] : S[0] * S[1] * S[NCH - 1];
+  l += (T)nl * SM::log2(Lp);
+  if constexpr (FG) {
+    T fg_sum = 0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) fg_sum += h[c] * (T)Kt[3][c][b];
+    v3 += fg_sum * (T)e_fg;
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if constexpr (MODE == kSplit) {
+      T a = 0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) a += h[c] * (T)Kt[g][c][b];
+      gq[g] = a * e[g];
+    } else {
+      const bool noise = MODE == kShared ? g == 0 : g < 3;
+      if (noise) {
+        T ao = 0, at = 0;
+        if constexpr (MODE == kShared) {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            ao += h[c] * (T)Kt[0][c][b];
+            at += h[c] * (T)Kt[1][c][b];
+          }
+        } else {
+          ao = h[g] * (T)Kt[0][g][b];
+          at = h[g] * (T)Kt[1][g][b];
+        }
+        const T ro_ = (T)w_oms * ao * e[g], rt_ = (T)w_tm * at * e[g];
+        v1 += ro_;
+        v2 += rt_;
+        gq[g] = ro_ + rt_;
+      } else {
+        T a = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) a += h[c] * (T)Kt[2][c][b];
+        gq[g] = a * e[g];
+      }
+    }
+  }
+  return l;
+}
+
+// Inputs and outputs of the double-range redo of one lane (passed by value to
+// an out-of-line function, so that the rare redo adds nothing to the register
+// budget of the common path).
+template <int G, int NT, int NCH, int B>
+struct WideLane {
+  float qe[G][B];
+  float Kt[NT][NCH][B];
+  float ND[NCH][B];
+  float NL[B];
+  float w_oms, w_tm, e_fg;
+};
+template <int G, int B>
+struct WideOut {
+  double l, v1, v2, v3;
+  float gq[G][B];
+};
+
+template <int MODE, int NCH, bool FG, int G, int NT, int B>
+__device__ __noinline__ WideOut<G, B> redo_lane_wide(WideLane<G, NT, NCH, B> in) {
+  WideOut<G, B> o;
+  o.l = o.v1 = o.v2 = o.v3 = 0.0;
+  // one bin at a time (the inputs live in the by-value copy): few registers
+#pragma unroll 1
+  for (int b = 0; b < B; ++b) {
+    float qx[G];
+    double gq[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) qx[g] = in.qe[g][b];
+    o.l += bin_score<double, true, MODE, NCH, FG, G, NT, B>(b, qx, in.Kt, in.ND, in.NL[b], in.w_oms, in.w_tm, in.e_fg,
+                                                      o.v1, o.v2, o.v3, gq);
+#pragma unroll
+    for (int g = 0; g < G; ++g) o.gq[g][b] = (float)gq[g];
+  }
+  return o;
+}
+
 template <typename R, int MODE, int NCH, bool FG, int B>
 __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_tiles, int tile, int K, int k_pad,
                                               int ref_chunk, const R* __restrict__ tab,
@@ -76,7 +244,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
                                               const R* __restrict__ coef, const int32_t* __restrict__ n_int,
                                               const StateScalars* __restrict__ scal, R* __restrict__ rec,
                                               int2* __restrict__ gidx, double* __restrict__ glast,
-                                              double* __restrict__ moments) {
+                                              double* __restrict__ moments, double* __restrict__ lrec) {
   constexpr int G = Groups<MODE>::G;
   constexpr int NT = FG ? 4 : 3;
   constexpr int CH = kWave * B;
@@ -197,8 +365,8 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
       }
       const bool crossing = (cross_state >> (q * G)) & 1ull;
 
-      // group factors E and piece abscissae T (t = x - x_piece) per bin
-      R E[G][B], T[G][B];
+      // group exponents Q (factors 2^Q) and piece abscissae T (t = x - x_piece) per bin
+      R Qe[G][B], T[G][B];
       if (!crossing) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -207,7 +375,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             T[g][b] = xr[b] + o0;
-            E[g][b] = Math<R>::exp2_(c0.x + T[g][b] * (c0.y + T[g][b] * (c0.z + T[g][b] * c0.w)));
+            Qe[g][b] = c0.x + T[g][b] * (c0.y + T[g][b] * (c0.z + T[g][b] * c0.w));
           }
         }
       } else {
@@ -226,13 +394,13 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
               const bool second = xr[b] >= lim;
               const R4 cc = second ? c1 : c0;
               T[g][b] = xr[b] + (second ? o1 : o0);
-              E[g][b] = Math<R>::exp2_(cc.x + T[g][b] * (cc.y + T[g][b] * (cc.z + T[g][b] * cc.w)));
+              Qe[g][b] = cc.x + T[g][b] * (cc.y + T[g][b] * (cc.z + T[g][b] * cc.w));
             }
           } else {         // several breakpoints: each piece from memory, select per bin
             const int i0 = __builtin_amdgcn_readlane(pi0, pl);
             const int i1 = __builtin_amdgcn_readlane(pi1, pl);
             const size_t base = (size_t)(s * G + g) * kMaxKnots;
-            R Q[B];
+            R Q[B] = {};
             for (int j = i0; j <= i1; ++j) {
               const R* cf = coef + (base + j) * 4;
               const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
@@ -249,7 +417,7 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
               }
             }
 #pragma unroll
-            for (int b = 0; b < B; ++b) E[g][b] = Math<R>::exp2_(Q[b]);
+            for (int b = 0; b < B; ++b) Qe[g][b] = Q[b];
           }
         }
       }
@@ -259,79 +427,49 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
 #pragma unroll
       for (int i = 0; i < NV; ++i) vf[i] = 0;
       R gq_keep[G][B];
+      R l0 = 0;
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        R S[NCH];
+        R qx[G], gq[G];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) S[c] = FG ? Kt[3][c][b] * e_fg : (R)0;
+        for (int g = 0; g < G; ++g) qx[g] = Qe[g][b];
+        l0 += bin_score<R, false, MODE, NCH, FG, G, NT, B>(b, qx, Kt, ND, NL[b], w_oms, w_tm, e_fg, vf[1], vf[2], vf[3], gq);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          if constexpr (MODE == kSplit) {
+        for (int g = 0; g < G; ++g) gq_keep[g][b] = gq[g];
+      }
+      // the lane's logL terms in double (the per-state sum runs over every chunk)
+      double ld = (double)l0;
+      if constexpr (kMixed) {
+        if (!isfinite(l0)) {
+          // A channel PSD left the single-precision range (an extreme state):
+          // redo the lane's bins with the group factors in double range (exact
+          // exponent, single-precision mantissa), so that such a state gets the
+          // status and values of the FP64 path.
+          WideLane<G, NT, NCH, B> in;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) S[c] += Kt[g][c][b] * E[g][b];
-          } else if constexpr (MODE == kShared) {
+          for (int b = 0; b < B; ++b) {
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-              S[c] += (g == 0 ? (w_oms * Kt[0][c][b] + w_tm * Kt[1][c][b]) : Kt[2][c][b]) * E[g][b];
-          } else {
-            if (g < 3) {
-              S[g] += (w_oms * Kt[0][g][b] + w_tm * Kt[1][g][b]) * E[g][b];
-            } else {
+            for (int g = 0; g < G; ++g) in.qe[g][b] = Qe[g][b];
 #pragma unroll
-              for (int c = 0; c < NCH; ++c) S[c] += Kt[2][c][b] * E[g][b];
-            }
+            for (int term = 0; term < NT; ++term)
+#pragma unroll
+              for (int c = 0; c < NCH; ++c) in.Kt[term][c][b] = Kt[term][c][b];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) in.ND[c][b] = ND[c][b];
+            in.NL[b] = NL[b];
           }
-        }
-        const R Nn = NL[b] * (R)(1.0 / kLn2);
-        R h[NCH];
+          in.w_oms = w_oms;
+          in.w_tm = w_tm;
+          in.e_fg = e_fg;
+          const WideOut<G, B> o = redo_lane_wide<MODE, NCH, FG, G, NT, B>(in);
+          ld = o.l;
+          vf[1] = (R)o.v1;
+          vf[2] = (R)o.v2;
+          vf[3] = (R)o.v3;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const R lw = (NCH == 2 && c == 0) ? (R)2 : (R)1;
-          const R r = Math<R>::rcp_(S[c]);
-          const R q1 = ND[c][b] * r;
-          vf[0] += q1 + (lw * NL[b]) * Math<R>::log2_(S[c]);
-          h[c] = (q1 - lw * Nn) * r;       // dlogL/dS~ (scaled units), A and E summed when merged
-        }
-        if constexpr (FG) {
-          R fg_sum = 0;
+          for (int b = 0; b < B; ++b)
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) fg_sum += h[c] * Kt[3][c][b];
-          vf[3] += fg_sum * e_fg;
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          R gq;
-          if constexpr (MODE == kSplit) {
-            R a = 0;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) a += h[c] * Kt[g][c][b];
-            gq = a * E[g][b];
-          } else {
-            const bool noise = MODE == kShared ? g == 0 : g < 3;
-            if (noise) {
-              R ao = 0, at = 0;
-              if constexpr (MODE == kShared) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                  ao += h[c] * Kt[0][c][b];
-                  at += h[c] * Kt[1][c][b];
-                }
-              } else {
-                ao = h[g] * Kt[0][g][b];
-                at = h[g] * Kt[1][g][b];
-              }
-              const R ro_ = w_oms * ao * E[g][b], rt_ = w_tm * at * E[g][b];
-              vf[1] += ro_;
-              vf[2] += rt_;
-              gq = ro_ + rt_;
-            } else {
-              R a = 0;
-#pragma unroll
-              for (int c = 0; c < NCH; ++c) a += h[c] * Kt[2][c][b];
-              gq = a * E[g][b];
-            }
-          }
-          gq_keep[g][b] = gq;
+            for (int g = 0; g < G; ++g) gq_keep[g][b] = o.gq[g][b];
         }
       }
       // moments of the first piece: bins before the next breakpoint
@@ -358,8 +496,15 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
       // a chunk inside one piece of every group needs no per-bin piece test
       if (crossing) accum_moments(std::true_type{});
       else accum_moments(std::false_type{});
-      // the lane sums (B bins each) are added over the wave in the working
-      // precision and stored in it (the finisher adds the records in double)
+      // the logL partial is added over the wave in double; the other lane sums
+      // (B bins each) in the working precision, stored in it (the finisher adds
+      // the records in double)
+      if constexpr (kMixed) {
+        const double lw = wave_sum(ld);
+        if (lane == 0) lrec[ro] = lw;
+      } else {
+        vf[0] = l0;
+      }
       const R red = reduce_scatter<M>(vf, lred[wv], lane);
       if ((lane & ((1 << (6 - M)) - 1)) == 0) rec[ro * NV + (lane >> (6 - M))] = red;
       {
@@ -502,12 +647,12 @@ __device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks
 template <typename RT>
 __global__ __launch_bounds__(256) void k_grad_finish(
     int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay, double x_knee,
-    const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+    const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, int64_t n_knots,
     const double* __restrict__ kx, const double* __restrict__ ky, const int32_t* __restrict__ n_int,
     const double* __restrict__ bx, const RT* __restrict__ rec, const int2* __restrict__ gidx,
-    const double* __restrict__ glast, const double* __restrict__ moments, const double* __restrict__ c0,
-    const uint32_t* __restrict__ status_ws, double* __restrict__ logL, double* __restrict__ dparams,
-    double* __restrict__ dkx, double* __restrict__ dky, uint32_t* __restrict__ status) {
+    const double* __restrict__ glast, const double* __restrict__ moments, const double* __restrict__ lrec,
+    const double* __restrict__ c0, const uint32_t* __restrict__ status_ws, double* __restrict__ logL,
+    double* __restrict__ dparams, double* __restrict__ dkx, double* __restrict__ dky, uint32_t* __restrict__ status) {
   __shared__ FinishLds L;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = uniform(threadIdx.x >> 6);
@@ -520,8 +665,10 @@ __global__ __launch_bounds__(256) void k_grad_finish(
     double ps[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = wv * kWave + lane; c < n_chunks; c += kWavesPerBlock * kWave) {
       const RT* r = rec + ((size_t)s * n_chunks + c) * NV;
+      // logL partials: a double array beside single-precision records, else slot 0
+      ps[0] += lrec ? lrec[(size_t)s * n_chunks + c] : (double)r[0];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ps[i] += (double)r[i];
+      for (int i = 1; i < 4; ++i) ps[i] += (double)r[i];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) ps[i] = wave_sum(ps[i]);
@@ -543,7 +690,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(
     if (wv == 0 && lane < n_params) dparams[lane * (size_t)n_states + s] = 0.0;
     for (int j = wv; j < n_spl; j += kWavesPerBlock) {
       int a, cn;
-      knot_range(off, kcnt, s * n_spl + j, a, cn);
+      knot_range(off, kcnt, s * n_spl + j, n_knots, a, cn);
       if (a < 0) continue;
       for (int i = lane; i < cn; i += kWave) {
         dkx[a + i] = 0.0;
@@ -591,7 +738,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(
   // spline knots: the moments of every group fed by the spline, summed in group order
   for (int j = wv; j < n_spl; j += kWavesPerBlock) {
     int a, n;
-    knot_range(off, kcnt, s * n_spl + j, a, n);
+    knot_range(off, kcnt, s * n_spl + j, n_knots, a, n);
     if (n == 0) continue;
     double M[4] = {0.0, 0.0, 0.0, 0.0};
     if (lane + 1 < n) {
@@ -607,7 +754,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(
 
 template <typename R, int B>
 hipError_t dispatch_grad(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, const R* tab, const R* coef,
-                         int NV, R* rec, int2* gidx, double* glast, hipStream_t s) {
+                         int NV, R* rec, int2* gidx, double* glast, double* lrec, hipStream_t s) {
   const Layout& L = ctx->lay;
   const int items = n_chunks * n_tiles;
   dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
@@ -615,7 +762,7 @@ hipError_t dispatch_grad(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int til
 #define LPS_GRAD(MODE, NCH, FG)                                                                            \
   hipLaunchKernelGGL((k_grad<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,       \
                      ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->n_int, ctx->scal, rec, \
-                     gidx, glast, ctx->moments)
+                     gidx, glast, ctx->moments, lrec)
   const bool fg = L.has_fg != 0;
   if (L.mode == kSplit && L.nch == 2 && !fg) LPS_GRAD(kSplit, 2, false);
   else if (L.mode == kSplit && L.nch == 2 && fg) LPS_GRAD(kSplit, 2, true);
@@ -663,6 +810,10 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
   char* base = (char*)ctx->gpartial;
   int2* gidx = (int2*)(base + ((rec_bytes + 15) & ~(size_t)15));
   double* glast = (double*)(gidx + (size_t)n * n_chunks * G);
+  // mixed path: per-(state, chunk) logL partials in double after the last-piece
+  // moments (single-precision records leave room for them in a layout sized
+  // for double records of half the chunk length)
+  double* lrec = mixed ? glast + (size_t)n * n_chunks * G * 4 : nullptr;
   long target = 8192;
   long tile = ((long)n * n_chunks) / target;
   if (tile < 1) tile = 1;
@@ -674,23 +825,23 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
   if (mixed) {
     float* rec = (float*)base;
     e = dispatch_grad<float, kBGrad32>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab32, ctx->coef32, NV, rec, gidx,
-                                       glast, s);
+                                       glast, lrec, s);
     if (e != hipSuccess) return e;
     timing_end(ctx, s);
     hipLaunchKernelGGL(k_grad_finish<float>, fgrid, fblock, 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
-                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
-                       ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams,
-                       dkx, dky, status);
+                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y,
+                       ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, lrec, ctx->c0, ctx->status_ws, logL,
+                       dparams, dkx, dky, status);
   } else {
     double* rec = (double*)base;
     e = dispatch_grad<double, kBGrad64>(ctx, n, n_chunks, n_tiles, (int)tile, ctx->tab64, ctx->coef64, NV, rec,
-                                        gidx, glast, s);
+                                        gidx, glast, nullptr, s);
     if (e != hipSuccess) return e;
     timing_end(ctx, s);
     hipLaunchKernelGGL(k_grad_finish<double>, fgrid, fblock, 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
-                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y,
-                       ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, ctx->c0, ctx->status_ws, logL, dparams,
-                       dkx, dky, status);
+                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y,
+                       ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, nullptr, ctx->c0, ctx->status_ws, logL,
+                       dparams, dkx, dky, status);
   }
   return hipGetLastError();
 }

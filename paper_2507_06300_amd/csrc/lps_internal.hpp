@@ -101,6 +101,7 @@ struct lps_ctx {
   double f_knee;
   double arm_length;
   double x_first, x_last;   // log10 of the first and last bin (coverage test)
+  double nk_uniform;        // the common N_k when every bin has the same one, else 0
   lps::Layout lay;
 
   // dataset copies (FP64)
@@ -171,6 +172,9 @@ bool valid_bins_per_lane(lps_precision prec, int b);
 constexpr int kWavesPerBlock = 4;
 constexpr int kB64 = 4;                        // bins per lane, FP64 kernel
 constexpr int kB32 = 8;                        // bins per lane, mixed kernel
+// Bins of a lane that share one reciprocal (and, with a uniform N_k, one
+// logarithm) in the batched forward kernel.
+constexpr int kMergeBins = 4;
 constexpr int kChunk64 = kWave * kB64;         // 256 bins per wave
 constexpr int kChunk32 = kWave * kB32;         // 512 bins per wave
 constexpr int kPlainBlock = 256;

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
     int K, const double* __restrict__ f, const double* __restrict__ nk, const double* __restrict__ D,
     const double* __restrict__ R, const double* __restrict__ Rfg, double L, double f_knee, int n_spl, int k_max,
     Route route, int n_states, int n_params, int s, const double* __restrict__ params,
-    const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
+    const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, int64_t n_knots, const double* __restrict__ kx,
     const double* __restrict__ ky, double* __restrict__ part) {
   __shared__ double red[kPlainBlock];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
     double P[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j < n_spl; ++j) {
       int a, n;
-      knot_range(off, kcnt, s * n_spl + j, a, n);
+      knot_range(off, kcnt, s * n_spl + j, n_knots, a, n);
       P[j] = (a >= 0) ? spline_value(kx + a, ky + a, n, k_max, xk) : 0.0;
     }
     const double ufg = n_params > 4 ? params[LPS_P_UFG * (size_t)n_states + s] : 0.0;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_bins(
 
 __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
     int n_blocks, const double* __restrict__ part, int s, int n_states, int n_spl, int k_max, int n_params,
-    const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+    const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, int64_t n_knots,
     const double* __restrict__ kx, const double* __restrict__ ky, const double* __restrict__ f, int K,
     double* __restrict__ logL,
     uint32_t* __restrict__ status) {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_finish(
   if (threadIdx.x == 0) {
     // band edges for the coverage test: log10 of the first and last bin
     const double x_first = log10(f[0]), x_last = log10(f[K - 1]);
-    uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kcnt, kx, ky, x_first, x_last);
+    uint32_t st = validate_state(s, n_states, n_spl, k_max, n_params, params, off, kcnt, n_knots, kx, ky, x_first, x_last);
     const double v = -red[0];
     if (st == 0 && !isfinite(v)) st |= LPS_ST_PSD;
     logL[s] = st ? -INFINITY : v;
@@ -142,9 +142,9 @@ hipError_t launch_plain_core(const PlainData& d, const lps_states* st, double* p
   for (int i = 0; i < n; ++i) {
     hipLaunchKernelGGL(k_plain_bins, dim3(nb), dim3(kPlainBlock), 0, s, d.K, d.f, d.nk, d.D, d.R, d.Rfg, d.L,
                        d.f_knee, d.n_spl, d.k_max, d.route, n, d.n_params, i, st->params, st->knot_off,
-                       st->knot_cnt, st->knot_x, st->knot_y, part);
+                       st->knot_cnt, st->n_knots, st->knot_x, st->knot_y, part);
     hipLaunchKernelGGL(k_plain_finish, dim3(1), dim3(kPlainBlock), 0, s, nb, part, i, n, d.n_spl, d.k_max,
-                       d.n_params, st->params, st->knot_off, st->knot_cnt, st->knot_x, st->knot_y, d.f, d.K, logL,
+                       d.n_params, st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y, d.f, d.K, logL,
                        status);
   }
   return hipGetLastError();
@@ -216,7 +216,7 @@ extern "C" lps_status lps_loglike_plain_fp64_noalloc(const lps_dataset_desc* d, 
       const int j = d->route[t][c];
       if (j < -1 || j >= d->n_spl || (t == LPS_TERM_FG && j != -1)) return LPS_E_ROUTING;
     }
-  if (st->n_states < 0) return LPS_E_SHAPE;
+  if (st->n_states < 0 || st->n_knots < 0) return LPS_E_SHAPE;
   if (st->n_states == 0) return LPS_OK;
   if (!st->params || !st->knot_off || !logL) return LPS_E_NULL;
   if (d->n_spl > 0 && (!st->knot_x || !st->knot_y)) return LPS_E_NULL;

@@ -529,7 +529,8 @@ __global__ void k_advance(unsigned long long* sweep) {
 
 // Initial state: packed CSR input -> padded slots.
 __global__ void k_load(lps_sampler sm, const double* __restrict__ params, const int32_t* __restrict__ off,
-                       const double* __restrict__ kx, const double* __restrict__ ky, int32_t* __restrict__ bad) {
+                       int64_t n_knots, const double* __restrict__ kx, const double* __restrict__ ky,
+                       int32_t* __restrict__ bad) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= sm.C) return;
   for (int q = 0; q < sm.P; ++q) sm.cp[q * (size_t)sm.C + c] = params[q * (size_t)sm.C + c];
@@ -537,7 +538,7 @@ __global__ void k_load(lps_sampler sm, const double* __restrict__ params, const 
     const int a = off[c * sm.NS + j];
     const int n = off[c * sm.NS + j + 1] - a;
     const int d = sm.off[c * sm.NS + j];
-    if (n == 1 || n < 0 || n > sm.KC) {   // 0 = disabled spline
+    if (n == 1 || n < 0 || n > sm.KC || a < 0 || (int64_t)a + n > n_knots) {   // 0 = disabled spline
       atomicOr(bad, 1);
       sm.ccnt[c * sm.NS + j] = 0;
       continue;
@@ -582,6 +583,7 @@ lps_states proposal_states(const lps_sampler* sm) {
   s.knot_x = sm->px;
   s.knot_y = sm->py;
   s.knot_cnt = sm->pcnt;
+  s.n_knots = (int64_t)sm->C * sm->NS * sm->KC;
   return s;
 }
 
@@ -593,6 +595,7 @@ lps_states current_states(const lps_sampler* sm) {
   s.knot_x = sm->cx;
   s.knot_y = sm->cy;
   s.knot_cnt = sm->ccnt;
+  s.n_knots = (int64_t)sm->C * sm->NS * sm->KC;
   return s;
 }
 
@@ -691,12 +694,12 @@ lps_status lps_sampler_destroy(lps_sampler* sm) {
 
 lps_status lps_sampler_set_state(lps_sampler* sm, const lps_states* init, uint64_t sweep_index, void* stream) {
   if (!sm || !init || !init->params || !init->knot_off || !init->knot_x || !init->knot_y) return LPS_E_NULL;
-  if (init->n_states != sm->C || init->knot_cnt) return LPS_E_SHAPE;
+  if (init->n_states != sm->C || init->knot_cnt || init->n_knots < 0) return LPS_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
   int32_t* bad = (int32_t*)sm->flag;   // reused as a flag word before any sweep
   if (hipMemsetAsync(bad, 0, 4, s) != hipSuccess) return LPS_E_DEVICE;
   hipLaunchKernelGGL(lps::k_load, lps::grid_for(sm->C, 64), dim3(64), 0, s, *sm, init->params, init->knot_off,
-                     init->knot_x, init->knot_y, bad);
+                     init->n_knots, init->knot_x, init->knot_y, bad);
   int32_t hb = 0;
   if (hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
     return LPS_E_DEVICE;

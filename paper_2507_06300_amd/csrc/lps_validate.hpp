@@ -19,32 +19,44 @@ constexpr double kCoverSlack = 1e-9;
 
 // Knot range of spline slot i (= state * n_spl + spline): packed CSR when cnt is
 // NULL (count = off[i+1] - off[i]), padded CSR otherwise (count = cnt[i]).
-__device__ inline void knot_range(const int32_t* __restrict__ off, const int32_t* __restrict__ cnt, int i, int& a,
-                                  int& n) {
+// Returns false, with a = n = 0 so that nothing is read, when the range is not
+// inside the knot arrays [0, n_knots).
+__host__ __device__ inline bool knot_range(const int32_t* __restrict__ off, const int32_t* __restrict__ cnt, int i,
+                                           int64_t n_knots, int& a, int& n) {
   a = off[i];
   n = cnt ? cnt[i] : off[i + 1] - a;
+  if (a < 0 || n < 0 || (int64_t)a + n > n_knots) {
+    a = 0;
+    n = 0;
+    return false;
+  }
+  return true;
 }
 
-__device__ inline uint32_t validate_state(int s, int n_states, int n_spl, int k_max, int n_params,
-                                          const double* __restrict__ params, const int32_t* __restrict__ off,
-                                          const int32_t* __restrict__ kcnt, const double* __restrict__ kx, const double* __restrict__ ky,
-                                          double x_first, double x_last) {
+__host__ __device__ inline uint32_t validate_state(int s, int n_states, int n_spl, int k_max, int n_params,
+                                                   const double* __restrict__ params, const int32_t* __restrict__ off,
+                                                   const int32_t* __restrict__ kcnt, int64_t n_knots,
+                                                   const double* __restrict__ kx, const double* __restrict__ ky,
+                                                   double x_first, double x_last) {
   uint32_t st = 0;
   for (int p = 0; p < n_params; ++p)
-    if (!isfinite(params[p * (size_t)n_states + s])) st |= LPS_ST_NONFINITE;
+    if (!__builtin_isfinite(params[p * (size_t)n_states + s])) st |= LPS_ST_NONFINITE;
   const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
   const double a_tm = params[LPS_P_ATM * (size_t)n_states + s];
   if (!(a_oms > 0.0 && a_tm > 0.0)) st |= LPS_ST_AMPLITUDE;
   for (int j = 0; j < n_spl; ++j) {
     int a, cnt;
-    knot_range(off, kcnt, s * n_spl + j, a, cnt);
+    if (!knot_range(off, kcnt, s * n_spl + j, n_knots, a, cnt)) {
+      st |= LPS_ST_COUNT;
+      continue;
+    }
     if (cnt == 0) continue;
-    if (a < 0 || cnt < 0 || cnt == 1 || cnt > k_max) {
+    if (cnt == 1 || cnt > k_max) {
       st |= LPS_ST_COUNT;
       continue;
     }
     bool fin = true;
-    for (int i = 0; i < cnt; ++i) fin = fin && isfinite(kx[a + i]) && isfinite(ky[a + i]);
+    for (int i = 0; i < cnt; ++i) fin = fin && __builtin_isfinite(kx[a + i]) && __builtin_isfinite(ky[a + i]);
     if (!fin) {
       st |= LPS_ST_NONFINITE;
       continue;
@@ -70,8 +82,9 @@ __device__ inline uint32_t wave_or(uint32_t v) {
 // every lane receives the state's status bits.
 __device__ inline uint32_t validate_state_wave(int lane, int s, int n_states, int n_spl, int k_max, int n_params,
                                                const double* __restrict__ params, const int32_t* __restrict__ off,
-                                               const int32_t* __restrict__ kcnt, const double* __restrict__ kx,
-                                               const double* __restrict__ ky, double x_first, double x_last) {
+                                               const int32_t* __restrict__ kcnt, int64_t n_knots,
+                                               const double* __restrict__ kx, const double* __restrict__ ky,
+                                               double x_first, double x_last) {
   uint32_t st = 0;
   if (lane < n_params && !isfinite(params[lane * (size_t)n_states + s])) st |= LPS_ST_NONFINITE;
   if (lane == 0) {
@@ -81,9 +94,12 @@ __device__ inline uint32_t validate_state_wave(int lane, int s, int n_states, in
   }
   for (int j = 0; j < n_spl; ++j) {
     int a, cnt;
-    knot_range(off, kcnt, s * n_spl + j, a, cnt);
+    if (!knot_range(off, kcnt, s * n_spl + j, n_knots, a, cnt)) {
+      if (lane == 0) st |= LPS_ST_COUNT;
+      continue;
+    }
     if (cnt == 0) continue;
-    if (a < 0 || cnt < 0 || cnt == 1 || cnt > k_max) {
+    if (cnt == 1 || cnt > k_max) {
       if (lane == 0) st |= LPS_ST_COUNT;
       continue;
     }
