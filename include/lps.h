@@ -60,7 +60,9 @@ typedef enum {
   LPS_E_PRECISION = 5,  /* unknown precision enum */
   LPS_E_DEVICE = 6,     /* a HIP runtime call failed */
   LPS_E_NOMEM = 7,      /* device allocation failed in lps_create */
-  LPS_E_STATE = 8       /* the call needs a state the batch does not provide */
+  LPS_E_STATE = 8,      /* the call needs a state the batch does not provide */
+  LPS_E_DATA = 9        /* dataset values out of their domain: N_k < 1 or not finite, D < 0 or
+                           not finite, a response or foreground entry not finite */
 } lps_status;
 
 typedef enum { LPS_FP64 = 0, LPS_MIXED = 1 } lps_precision;
@@ -153,7 +155,17 @@ lps_status lps_psd_build(lps_ctx* ctx, const lps_states* st /*[host]*/, int32_t 
                          double* S, double* Sn, double* Sh, uint32_t* status, void* stream);
 
 /*
- * logL[s] for every state in one batched launch.  LPS_FP64 evaluates every
+ * logL[s] for every state in one batched launch: the per-bin complex Wishart
+ * log-density of Sec. "MCMC setup" (minus the trace of C^-1 Y, minus nu log
+ * det C, the two unnumbered equations there) with the diagonal A/E/T
+ * covariance C_k = diag(S_A, S_E, S_T)(f_k) of Eq. (psd_tot) with Eqs.
+ * (splines), Y_k = N_k D_k and nu_k = N_k, summed over bins (the combined
+ * likelihood that follows them; N_k = 1 gives the Whittle likelihood):
+ *   logL = - sum_k sum_c N_k (D_ck / S_ck + ln S_ck).
+ * Inputs: st [host struct naming device arrays, see lps_states]; outputs
+ * logL[n_states] and status[n_states] [device, caller-owned].  Invalid
+ * states get logL = -inf and their LPS_ST_* bits; a malformed batch returns
+ * LPS_E_SHAPE / LPS_E_CAPACITY before anything is launched.  LPS_FP64 evaluates every
  * per-bin term in double precision; LPS_MIXED evaluates them in single
  * precision in per-bin scaled units (hardware exp2/log2/rcp) and keeps the
  * per-state bin reduction and the scaling constant in double precision.
@@ -163,7 +175,10 @@ lps_status lps_loglike_batch(lps_ctx* ctx, const lps_states* st /*[host]*/, lps_
                              double* logL, uint32_t* status, void* stream);
 
 /*
- * logL and its gradient (hand-written adjoint):
+ * logL of lps_loglike_batch and its gradient with respect to every state
+ * input (hand-written adjoint of the same sum: the template derivatives of
+ * Eqs. (noise_tdi), (pl), (Sh), the spline derivatives of App. A with
+ * respect to knot abscissae and heights, chained through Eq. (splines)):
  *   dparams[p][s]   = dlogL/d params[p][s]   (same layout as params)
  *   dknot_x[i], dknot_y[i] = dlogL/d knot_x[i], knot_y[i] (same CSR layout as
  *   the knots; edge abscissae get 0 because they are fixed).
@@ -174,7 +189,9 @@ lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st /*[host]*/,
                                   uint32_t* status, void* stream);
 
 /*
- * Reference path: plain FP64, one launch per state, one thread per bin,
+ * The likelihood of lps_loglike_batch (Sec. "MCMC setup", PSD of Eq.
+ * (psd_tot) with Eqs. (splines)) on the reference path: plain FP64, one
+ * launch per state, one thread per bin,
  * every factor evaluated from f_k (sin, cos, pow, exp10, log), a binary
  * search and a local Akima stencil per bin, and a two-pass reduction.
  */
@@ -317,6 +334,17 @@ lps_status lps_stepping_stone(const double* betas, int32_t n_temps, const double
  * DIC = mean D + p_D, Var D.  LPS_E_SHAPE for a rung outside [0, n_temps). */
 lps_status lps_dic(const double* logL, int32_t n_rec, int32_t n_temps, int32_t n_walkers, int32_t rung,
                    const double* logL_at_mean, double* out, void* stream);
+
+/* The 20-rung inverse-temperature ladder of Sec. "MCMC setup" [host output,
+ * 20 values, increasing]: 5 log-spaced from 1e-20 up to (not including) 1e-12,
+ * 10 from 1e-12 up to 1e-5, 5 from 1e-5 to 1 inclusive. */
+lps_status lps_paper_ladder(double* betas /*[host]*/);
+
+/* Median of each of m columns x[col * ld + i], i < n (device input and output
+ * out[m]; the mean of the two middle values when n is even), as used for the
+ * step-1 summary of Sec. "Two-step inference".  Asynchronous on `stream`, no
+ * allocation; O(n^2) per column, n <= 65536 (LPS_E_SHAPE beyond). */
+lps_status lps_column_median(const double* x, int32_t n, int32_t m, int32_t ld, double* out, void* stream);
 
 /*
  * Data stage: from TDI time series to the inputs of lps_create.

@@ -27,7 +27,8 @@ _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 ST_COUNT, ST_ORDER, ST_COVER, ST_NONFINITE, ST_AMPLITUDE, ST_PSD = 1, 2, 4, 8, 16, 32
 
 _STATUS_NAMES = {0: "LPS_OK", 1: "LPS_E_NULL", 2: "LPS_E_SHAPE", 3: "LPS_E_CAPACITY", 4: "LPS_E_ROUTING",
-                 5: "LPS_E_PRECISION", 6: "LPS_E_DEVICE", 7: "LPS_E_NOMEM", 8: "LPS_E_STATE"}
+                 5: "LPS_E_PRECISION", 6: "LPS_E_DEVICE", 7: "LPS_E_NOMEM", 8: "LPS_E_STATE",
+                 9: "LPS_E_DATA"}
 
 
 class LpsError(RuntimeError):
@@ -75,7 +76,8 @@ SYMBOLS = ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "l
            "lps_data_periodogram", "lps_data_average", "lps_data_response",
            "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch", "lps_cov_build",
            "lps_math64_check", "lps_loglike_plain_fp64_noalloc",
-           "lps_data_create", "lps_data_destroy", "lps_data_periodogram_planned"]
+           "lps_data_create", "lps_data_destroy", "lps_data_periodogram_planned", "lps_paper_ladder",
+           "lps_column_median"]
 
 _lib = None
 
@@ -136,12 +138,14 @@ def lib():
     L.lps_data_create.argtypes = [i32, i32, ctypes.c_int, ctypes.POINTER(vp)]
     L.lps_data_destroy.argtypes = [vp]
     L.lps_data_periodogram_planned.argtypes = [vp, vp, ctypes.c_double, vp, i32, vp, vp]
+    L.lps_paper_ladder.argtypes = [vp]
+    L.lps_column_median.argtypes = [vp, i32, i32, i32, vp, vp]
     for name in ["lps_sampler_create", "lps_sampler_destroy", "lps_sampler_set_state", "lps_sampler_sweep",
                  "lps_sampler_get_state", "lps_sampler_counters", "lps_philox4x32_10", "lps_stepping_stone",
                  "lps_dic", "lps_data_periodogram", "lps_data_average", "lps_data_response",
                  "lps_cov_create", "lps_cov_destroy", "lps_cov_loglike_batch", "lps_cov_loglike_grad_batch",
                  "lps_cov_build", "lps_math64_check", "lps_loglike_plain_fp64_noalloc", "lps_data_create",
-                 "lps_data_destroy", "lps_data_periodogram_planned"]:
+                 "lps_data_destroy", "lps_data_periodogram_planned", "lps_paper_ladder", "lps_column_median"]:
         getattr(L, name).restype = st
     for name in ["lps_create", "lps_destroy", "lps_psd_build", "lps_loglike_batch", "lps_loglike_grad_batch",
                  "lps_loglike_plain_fp64", "lps_set_timing", "lps_kernel_time_ms", "lps_get_error"]:
@@ -595,10 +599,22 @@ def data_response(grid_f, grid_R, f: torch.Tensor, stream=None):
 
 
 def paper_ladder():
-    """Inverse temperatures of the 20-rung ladder of Sec. "MCMC setup" (increasing):
-    5 log-spaced from 1e-20, 10 from 1e-12, 5 from 1e-5 up to 1."""
-    return np.concatenate([np.logspace(-20, -12, 5, endpoint=False), np.logspace(-12, -5, 10, endpoint=False),
-                           np.logspace(-5, 0, 5)])
+    """Inverse temperatures of the 20-rung ladder of Sec. "MCMC setup" (increasing),
+    from lps_paper_ladder."""
+    out = np.empty(20, dtype=np.float64)
+    _check(lib().lps_paper_ladder(out.ctypes.data), "lps_paper_ladder")
+    return out
+
+
+def column_median(x: torch.Tensor, stream=None):
+    """Median of every row of x [m, n] (device FP64, contiguous), from lps_column_median:
+    returns a device tensor [m]."""
+    assert x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
+    xc = x.contiguous()
+    m, n = xc.shape
+    out = torch.empty(m, dtype=torch.float64, device=xc.device)
+    _check(lib().lps_column_median(_ptr(xc), int(n), int(m), int(n), _ptr(out), _stream(stream)), "lps_column_median")
+    return out
 
 
 def stepping_stone(betas, logL: torch.Tensor, stream=None):
@@ -676,7 +692,7 @@ class Sampler:
     def sweep(self, n=1, stream=None):
         _check(lib().lps_sampler_sweep(self._h, int(n), _stream(stream)), "lps_sampler_sweep")
 
-    def get_state(self, stream=None):
+    def get_state(self, stream=None, sweep_index=True):
         dev, C, NS, KC = self.ctx.device, self.C, self.ctx.n_spl, self.KC
         params = torch.empty((self.ctx.n_params, C), dtype=torch.float64, device=dev)
         off = torch.empty(C * NS, dtype=torch.int32, device=dev)
@@ -686,9 +702,10 @@ class Sampler:
         logL = torch.empty(C, dtype=torch.float64, device=dev)
         sw = ctypes.c_uint64()
         _check(lib().lps_sampler_get_state(self._h, _ptr(params), _ptr(off), _ptr(cnt), _ptr(kx), _ptr(ky),
-                                           _ptr(logL), ctypes.byref(sw), _stream(stream)), "lps_sampler_get_state")
+                                           _ptr(logL), ctypes.byref(sw) if sweep_index else None, _stream(stream)),
+               "lps_sampler_get_state")
         return {"params": params, "knot_off": off, "knot_cnt": cnt, "knot_x": kx, "knot_y": ky, "logL": logL,
-                "sweep": sw.value}
+                "sweep": sw.value if sweep_index else None}
 
     def record_logL(self, out_row: torch.Tensor, stream=None):
         """Copy the chains' current logL [T*W] into out_row (device FP64, e.g. a row
@@ -737,8 +754,12 @@ class LogLikeFn(torch.autograd.Function):
         dp, dkx, dky, knot_off = fctx.saved_tensors
         n = dp.shape[1]
         n_spl = fctx.n_spl
-        # per-knot state index from the CSR offsets: knots of state s lie in [off[s*n_spl], off[(s+1)*n_spl])
-        counts = (knot_off[n_spl::n_spl][:n] - knot_off[0:n * n_spl:n_spl]).to(torch.int64)
-        owner = torch.repeat_interleave(torch.arange(n, device=dp.device), counts)
-        g_knot = gout[owner]
+        if n_spl == 0:
+            return None, None, dp * gout[None, :], None, None, None
+        # owner state of every knot: knot i belongs to the state whose first slot
+        # offset is the last one <= i (offsets relative to knot_off[0])
+        first = (knot_off[0:n * n_spl:n_spl] - knot_off[0]).to(torch.int64)
+        idx = torch.arange(dkx.numel(), device=dp.device, dtype=torch.int64)
+        owner = torch.searchsorted(first, idx, right=True) - 1
+        g_knot = gout[owner.clamp(min=0)]
         return None, None, dp * gout[None, :], dkx * g_knot, dky * g_knot, None

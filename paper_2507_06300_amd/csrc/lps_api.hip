@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "lps_internal.hpp"
+#include "lps_roctx.hpp"
 
 using lps::Layout;
 
@@ -129,6 +130,7 @@ const char* lps_strerror(lps_status s) {
     case LPS_E_DEVICE: return "HIP runtime error";
     case LPS_E_NOMEM: return "device allocation failed";
     case LPS_E_STATE: return "state batch does not provide what the call needs";
+    case LPS_E_DATA: return "dataset values out of domain (N_k >= 1, D >= 0, finite D, R and Rfg)";
   }
   return "unknown status";
 }
@@ -142,6 +144,7 @@ int32_t lps_last_device_error(const char** name) {
 int32_t lps_chunk_bins(lps_precision prec) { return prec == LPS_MIXED ? lps::kChunk32 : lps::kChunk64; }
 
 lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
+  LPS_API_RANGE();
   if (!d || !out) return LPS_E_NULL;
   *out = nullptr;
   if (!d->f || !d->nk || !d->D || !d->R) return LPS_E_NULL;
@@ -155,13 +158,17 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   bool ae_equal = true;
   double nk_uniform = 0.0;
   {
-    std::vector<double> h(2 * (size_t)K);
-    const double* tabs[2] = {d->R, d->Rfg};
-    for (int i = 0; i < 2 && ae_equal; ++i) {
+    // per-channel tables: finite values (D also >= 0); A and E merge when their
+    // response (and foreground) rows agree bitwise
+    std::vector<double> h(3 * (size_t)K);
+    const double* tabs[3] = {d->R, d->Rfg, d->D};
+    for (int i = 0; i < 3; ++i) {
       if (!tabs[i]) continue;
-      if (hipMemcpy(h.data(), tabs[i], 2 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      if (hipMemcpy(h.data(), tabs[i], 3 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         return LPS_E_DEVICE;
-      ae_equal = memcmp(h.data(), h.data() + K, (size_t)K * sizeof(double)) == 0;
+      for (size_t q = 0; q < 3 * (size_t)K; ++q)
+        if (!std::isfinite(h[q]) || (i == 2 && h[q] < 0.0)) return LPS_E_DATA;
+      if (i < 2) ae_equal = ae_equal && memcmp(h.data(), h.data() + K, (size_t)K * sizeof(double)) == 0;
     }
     std::vector<double> fh(K);
     if (hipMemcpy(fh.data(), d->f, (size_t)K * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
@@ -172,7 +179,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
       return LPS_E_DEVICE;
     nk_uniform = fh[0];
     for (int k = 0; k < K; ++k) {
-      if (!(fh[k] >= 1.0) || !std::isfinite(fh[k])) return LPS_E_SHAPE;   // N_k >= 1
+      if (!(fh[k] >= 1.0) || !std::isfinite(fh[k])) return LPS_E_DATA;   // N_k >= 1
       if (fh[k] != fh[0]) nk_uniform = 0.0;
     }
   }
@@ -266,6 +273,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
 }
 
 lps_status lps_destroy(lps_ctx* ctx) {
+  LPS_API_RANGE();
   if (!ctx) return LPS_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
@@ -275,6 +283,7 @@ lps_status lps_destroy(lps_ctx* ctx) {
 
 lps_status lps_psd_build(lps_ctx* ctx, const lps_states* st, int32_t k0, int32_t k1, double* S, double* Sn,
                          double* Sh, uint32_t* status, void* stream) {
+  LPS_API_RANGE();
   lps_status r = check_states(ctx, st);
   if (r != LPS_OK) return r;
   if (k0 < 0 || k1 > ctx->n_bins || k0 > k1) return LPS_E_SHAPE;
@@ -285,6 +294,7 @@ lps_status lps_psd_build(lps_ctx* ctx, const lps_states* st, int32_t k0, int32_t
 
 lps_status lps_loglike_batch(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL,
                              uint32_t* status, void* stream) {
+  LPS_API_RANGE();
   lps_status r = check_states(ctx, st);
   if (r != LPS_OK) return r;
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
@@ -296,6 +306,7 @@ lps_status lps_loglike_batch(lps_ctx* ctx, const lps_states* st, lps_precision p
 lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st, lps_precision prec, double* logL,
                                   double* dparams, double* dknot_x, double* dknot_y, uint32_t* status,
                                   void* stream) {
+  LPS_API_RANGE();
   lps_status r = check_states(ctx, st);
   if (r != LPS_OK) return r;
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
@@ -309,6 +320,7 @@ lps_status lps_loglike_grad_batch(lps_ctx* ctx, const lps_states* st, lps_precis
 
 lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st, double* logL, uint32_t* status,
                                   void* stream) {
+  LPS_API_RANGE();
   lps_status r = check_states(ctx, st);
   if (r != LPS_OK) return r;
   if (st->n_states == 0) return LPS_OK;
@@ -317,6 +329,7 @@ lps_status lps_loglike_plain_fp64(lps_ctx* ctx, const lps_states* st, double* lo
 }
 
 lps_status lps_set_launch(lps_ctx* ctx, lps_precision prec, int32_t bins_per_lane, int32_t states_per_tile) {
+  LPS_API_RANGE();
   if (!ctx) return LPS_E_NULL;
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
   if (bins_per_lane != 0 && !lps::valid_bins_per_lane(prec, bins_per_lane)) return LPS_E_SHAPE;
@@ -327,6 +340,7 @@ lps_status lps_set_launch(lps_ctx* ctx, lps_precision prec, int32_t bins_per_lan
 
 lps_status lps_get_launch(lps_ctx* ctx, lps_precision prec, int32_t n_states, int32_t* bins_per_lane,
                           int32_t* states_per_tile) {
+  LPS_API_RANGE();
   if (!ctx || !bins_per_lane || !states_per_tile) return LPS_E_NULL;
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
   if (n_states < 1) return LPS_E_SHAPE;
@@ -338,6 +352,7 @@ lps_status lps_get_launch(lps_ctx* ctx, lps_precision prec, int32_t n_states, in
 
 lps_status lps_autotune(lps_ctx* ctx, const lps_states* st, lps_precision prec, int32_t reps, double* best_ms,
                         void* stream) {
+  LPS_API_RANGE();
   lps_status r = check_states(ctx, st);
   if (r != LPS_OK) return r;
   if (prec != LPS_FP64 && prec != LPS_MIXED) return LPS_E_PRECISION;
@@ -390,6 +405,7 @@ lps_status lps_autotune(lps_ctx* ctx, const lps_states* st, lps_precision prec, 
 }
 
 lps_status lps_set_timing(lps_ctx* ctx, int enable) {
+  LPS_API_RANGE();
   if (!ctx) return LPS_E_NULL;
   ctx->timing = enable ? 1 : 0;
   ctx->time_ms = 0.0;
@@ -398,6 +414,7 @@ lps_status lps_set_timing(lps_ctx* ctx, int enable) {
 }
 
 lps_status lps_kernel_time_ms(lps_ctx* ctx, double* total_ms, int32_t* launches) {
+  LPS_API_RANGE();
   if (!ctx || !total_ms || !launches) return LPS_E_NULL;
   *total_ms = ctx->time_ms;
   *launches = ctx->time_launches;
@@ -405,6 +422,7 @@ lps_status lps_kernel_time_ms(lps_ctx* ctx, double* total_ms, int32_t* launches)
 }
 
 lps_status lps_get_error(lps_ctx* ctx, void* stream, uint32_t* sticky_flags) {
+  LPS_API_RANGE();
   if (!ctx || !sticky_flags) return LPS_E_NULL;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return LPS_E_DEVICE;
   uint32_t v = 0;

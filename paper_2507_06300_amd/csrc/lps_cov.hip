@@ -56,6 +56,7 @@
 #include "lps_spline.hpp"
 #include "lps_validate.hpp"
 #include "lps_cov_common.hpp"
+#include "lps_roctx.hpp"
 
 
 namespace lps {
@@ -409,6 +410,7 @@ using namespace lps::covk;
 extern "C" {
 
 lps_status lps_cov_create(const lps_cov_desc* d, int device, lps_cov_ctx** out) {
+  LPS_API_RANGE();
   using namespace lps;
   if (!d || !out) return LPS_E_NULL;
   *out = nullptr;
@@ -498,6 +500,7 @@ lps_status lps_cov_create(const lps_cov_desc* d, int device, lps_cov_ctx** out) 
 }
 
 lps_status lps_cov_destroy(lps_cov_ctx* c) {
+  LPS_API_RANGE();
   if (!c) return LPS_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
@@ -510,6 +513,7 @@ lps_status lps_cov_destroy(lps_cov_ctx* c) {
 
 lps_status lps_cov_loglike_batch(lps_cov_ctx* c, const lps_states* st, double* logL, uint32_t* status,
                                  void* stream) {
+  LPS_API_RANGE();
   using namespace lps;
   lps_status cs = check_cov_states(c, st);
   if (cs != LPS_OK) return cs;
@@ -531,6 +535,7 @@ lps_status lps_cov_loglike_batch(lps_cov_ctx* c, const lps_states* st, double* l
 
 lps_status lps_cov_build(lps_cov_ctx* c, const lps_states* st, int32_t k0, int32_t k1, double* C, uint32_t* status,
                          void* stream) {
+  LPS_API_RANGE();
   using namespace lps;
   lps_status cs = check_cov_states(c, st);
   if (cs != LPS_OK) return cs;

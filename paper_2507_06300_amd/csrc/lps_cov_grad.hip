@@ -10,6 +10,7 @@
 #include "lps_spline_back.hpp"
 #include "lps_validate.hpp"
 #include "lps_cov_common.hpp"
+#include "lps_roctx.hpp"
 
 namespace lps {
 namespace {
@@ -384,6 +385,7 @@ extern "C" {
 
 lps_status lps_cov_loglike_grad_batch(lps_cov_ctx* c, const lps_states* st, double* logL, double* dparams,
                                       double* dknot_x, double* dknot_y, uint32_t* status, void* stream) {
+  LPS_API_RANGE();
   using namespace lps;
   lps_status cs = check_cov_states(c, st);
   if (cs != LPS_OK) return cs;

@@ -17,6 +17,7 @@
 #include <math.h>
 
 #include "lps_internal.hpp"
+#include "lps_roctx.hpp"
 
 namespace lps {
 namespace {
@@ -175,6 +176,7 @@ lps_status periodogram_on(lps_data_ctx* c, const double* x, double dt, const dou
 extern "C" {
 
 lps_status lps_data_create(int32_t n_ch, int32_t n_t, int device, lps_data_ctx** out) {
+  LPS_API_RANGE();
   if (!out) return LPS_E_NULL;
   *out = nullptr;
   if (n_ch < 1 || n_t < 2) return LPS_E_SHAPE;
@@ -232,6 +234,7 @@ lps_status lps_data_create(int32_t n_ch, int32_t n_t, int device, lps_data_ctx**
 }
 
 lps_status lps_data_destroy(lps_data_ctx* ctx) {
+  LPS_API_RANGE();
   if (!ctx) return LPS_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
@@ -241,6 +244,7 @@ lps_status lps_data_destroy(lps_data_ctx* ctx) {
 
 lps_status lps_data_periodogram_planned(lps_data_ctx* ctx, const double* x, double dt, const double* window,
                                         int32_t xyz_to_aet, double* P, void* stream) {
+  LPS_API_RANGE();
   if (!ctx || !x || !P) return LPS_E_NULL;
   if (!(dt > 0.0) || (xyz_to_aet && ctx->n_ch != 3)) return LPS_E_SHAPE;
   return periodogram_on(ctx, x, dt, window, xyz_to_aet, P, (hipStream_t)stream);
@@ -248,6 +252,7 @@ lps_status lps_data_periodogram_planned(lps_data_ctx* ctx, const double* x, doub
 
 lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, double dt, const double* window,
                                 int32_t xyz_to_aet, double* P, void* stream) {
+  LPS_API_RANGE();
   if (!x || !P) return LPS_E_NULL;
   if (n_ch < 1 || n_t < 2 || !(dt > 0.0) || (xyz_to_aet && n_ch != 3)) return LPS_E_SHAPE;
   int device = 0;
@@ -266,6 +271,7 @@ lps_status lps_data_periodogram(const double* x, int32_t n_ch, int32_t n_t, doub
 
 lps_status lps_data_average(const double* P, int32_t n_ch, int32_t n_f, const double* f, int32_t k0, int32_t seg_len,
                             int32_t n_seg, double* D, double* f_seg, double* nu, void* stream) {
+  LPS_API_RANGE();
   if (!P || !f || !D) return LPS_E_NULL;
   if (n_ch < 1 || n_f < 1 || k0 < 0 || seg_len < 1 || n_seg < 1 || (long)k0 + (long)seg_len * n_seg > n_f)
     return LPS_E_SHAPE;
@@ -276,6 +282,7 @@ lps_status lps_data_average(const double* P, int32_t n_ch, int32_t n_f, const do
 
 lps_status lps_data_response(const double* grid_f, const double* grid_R, int32_t n_ch, int32_t n_g, const double* f,
                              int32_t n, double* R, void* stream) {
+  LPS_API_RANGE();
   if (!grid_f || !grid_R || !f || !R) return LPS_E_NULL;
   if (n_ch < 1 || n_g < 2 || n < 1) return LPS_E_SHAPE;
   hipLaunchKernelGGL(lps::k_response, lps::blocks_for((long)n_ch * n, 256), dim3(256), 0, (hipStream_t)stream, n_ch,

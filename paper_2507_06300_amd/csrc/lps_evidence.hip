@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "lps_internal.hpp"
+#include "lps_roctx.hpp"
 
 namespace lps {
 namespace {
@@ -126,13 +127,74 @@ __global__ __launch_bounds__(kRedThreads) void k_dic(int T, int n_rec, int W, in
   }
 }
 
+// Median of each of m columns x[col * ld + i], i < n (numpy's definition: the
+// middle value, or the mean of the two middle values for even n).  One block
+// per column; a value is the k-th smallest when fewer than k + 1 values are
+// below it and more than k are at or below it, and among equal values the one
+// with the lowest index reports it, so no two threads write one output.
+__global__ __launch_bounds__(kRedThreads) void k_column_median(int n, int ld, const double* __restrict__ x,
+                                                               double* __restrict__ out) {
+  __shared__ double pick[2];
+  const double* col = x + (size_t)blockIdx.x * ld;
+  const int k_lo = (n - 1) / 2, k_hi = n / 2;
+  for (int i = threadIdx.x; i < n; i += kRedThreads) {
+    const double v = col[i];
+    int lt = 0, le = 0, eq_before = 0;
+    for (int j = 0; j < n; ++j) {
+      const double u = col[j];
+      lt += u < v;
+      le += u <= v;
+      eq_before += (u == v) && (j < i);
+    }
+    if (eq_before == 0) {
+      if (lt <= k_lo && k_lo < le) pick[0] = v;
+      if (lt <= k_hi && k_hi < le) pick[1] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = 0.5 * (pick[0] + pick[1]);
+}
+
 }  // namespace
 }  // namespace lps
 
 extern "C" {
 
+// The 20 rungs of the ladder of Sec. "MCMC setup", increasing: 5 log-spaced
+// from 1e-20 (up to, not including, 1e-12), 10 from 1e-12 (up to 1e-5), 5 from
+// 1e-5 to 1 inclusive.
+lps_status lps_paper_ladder(double* betas) {
+  LPS_API_RANGE();
+  if (!betas) return LPS_E_NULL;
+  struct Group {
+    double lo, hi;
+    int num;
+    bool endpoint;
+  };
+  const Group groups[3] = {{-20.0, -12.0, 5, false}, {-12.0, -5.0, 10, false}, {-5.0, 0.0, 5, true}};
+  int k = 0;
+  for (const Group& g : groups) {
+    const int div = g.endpoint ? g.num - 1 : g.num;
+    const double step = (g.hi - g.lo) / div;
+    for (int i = 0; i < g.num; ++i) {
+      const double e = (g.endpoint && i == g.num - 1) ? g.hi : g.lo + i * step;
+      betas[k++] = pow(10.0, e);
+    }
+  }
+  return LPS_OK;
+}
+
+lps_status lps_column_median(const double* x, int32_t n, int32_t m, int32_t ld, double* out, void* stream) {
+  LPS_API_RANGE();
+  if (!x || !out) return LPS_E_NULL;
+  if (n < 1 || m < 1 || ld < n || n > (1 << 16)) return LPS_E_SHAPE;
+  hipLaunchKernelGGL(lps::k_column_median, dim3(m), dim3(lps::kRedThreads), 0, (hipStream_t)stream, n, ld, x, out);
+  return lps::device_status(hipGetLastError());
+}
+
 lps_status lps_stepping_stone(const double* betas, int32_t n_temps, const double* logL, int32_t n_rec,
                               int32_t n_walkers, double* out, void* stream) {
+  LPS_API_RANGE();
   if (!betas || !logL || !out) return LPS_E_NULL;
   if (n_temps < 2 || n_rec < 1 || n_walkers < 1) return LPS_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
@@ -147,6 +209,7 @@ lps_status lps_stepping_stone(const double* betas, int32_t n_temps, const double
 
 lps_status lps_dic(const double* logL, int32_t n_rec, int32_t n_temps, int32_t n_walkers, int32_t rung,
                    const double* logL_at_mean, double* out, void* stream) {
+  LPS_API_RANGE();
   if (!logL || !logL_at_mean || !out) return LPS_E_NULL;
   if (n_temps < 1 || n_rec < 1 || n_walkers < 1 || rung < 0 || rung >= n_temps) return LPS_E_SHAPE;
   hipLaunchKernelGGL(lps::k_dic, dim3(1), dim3(lps::kRedThreads), 0, (hipStream_t)stream, n_temps, n_rec, n_walkers,

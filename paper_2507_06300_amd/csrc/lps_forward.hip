@@ -30,6 +30,11 @@
 namespace lps {
 namespace {
 
+// A piece whose cubic term changes its exponent by at most this much (log2
+// units, about 1e-8 relative in 2^Q) anywhere in a chunk is evaluated as a
+// quadratic there.
+constexpr double kQuadTol = 1.0 / (1 << 26);
+
 // 2^q and log2(v) over the double-precision range with single-precision
 // accuracy: the integer part of the exponent is applied exactly (ldexp /
 // frexp) and only the fraction goes through the hardware transcendental.
@@ -207,8 +212,8 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   const int klast = min(kbase + CH, K) - 1;
   const double xf = x64[kbase];
   const double xl = x64[klast];
-  // abscissa origin of the single-precision table rows (start of their block)
-  const double xo = kMixed ? x64[(kbase / ref_chunk) * ref_chunk] : 0.0;
+  // abscissa origin of the single-precision table rows (midpoint of their block)
+  const double xo = kMixed ? block_origin(x64, (kbase / ref_chunk) * ref_chunk, K) : 0.0;
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);
@@ -218,6 +223,7 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     const size_t pbase = (size_t)((sub + ps) * G + pg) * kMaxKnots;
     const int pni = pv ? n_int[(sub + ps) * G + pg] : 0;
     int pi0 = 0, pi1 = 0;
+    bool pquad = true;
     if (pni > 0) {
       pi0 = count_le(bx + pbase, pni, xf);
       // the chunk usually ends in the piece it starts in: one more breakpoint
@@ -248,6 +254,11 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       R4 r4;
       R off;
       piece_rec(pi0, bx[pbase + pi0], r4, off);
+      if constexpr (kLocalPoly) {
+        // the cubic term d dx^3 over the chunk, |dx| <= half the block span
+        const double h = fmax(xl - xo, xo - xf);
+        pquad = fabs(coef64[(pbase + pi0) * 4 + 3]) * h * h * h <= kQuadTol;
+      }
       lcoef[wv][lane] = r4;
       if constexpr (!kLocalPoly) loff[wv][lane] = off;
       if (pi1 > pi0) {
@@ -271,10 +282,16 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     // pair lanes whose chunk straddles a breakpoint, and states that are invalid
     const unsigned long long straddle = __ballot(pv && pni > 0 && pi0 != pi1);
     const unsigned long long multi = __ballot(pv && pni > 0 && pi1 > pi0 + 1);
-    // bit q*G set when any group of state q crosses a breakpoint in this chunk
+    // bit q*G set when any group of state q crosses a breakpoint in this chunk,
+    // or needs the cubic term
     unsigned long long cross_state = straddle;
+    const unsigned long long cubic = __ballot(pv && pni > 0 && !pquad);
+    unsigned long long cubic_state = cubic;
 #pragma unroll
-    for (int g = 1; g < G; ++g) cross_state |= straddle >> g;
+    for (int g = 1; g < G; ++g) {
+      cross_state |= straddle >> g;
+      cubic_state |= cubic >> g;
+    }
     const unsigned long long invalid = __ballot(pv && pg == 0 && pni == 0);
     wave_lds_sync();
 
@@ -334,12 +351,25 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       };
       if (!((cross_state >> (q * G)) & 1ull)) {
         // the usual case: the chunk lies inside one piece of every group, so
-        // the state's body is straight-line code
+        // the state's body is straight-line code; where every group's cubic
+        // term is below kQuadTol over the chunk (high frequencies, where a
+        // chunk spans little of log10 f) the exponents are quadratics
+        if (kLocalPoly && !((cubic_state >> (q * G)) & 1ull)) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          R E[B];
-          uniform_E(q * G + g, E);
-          fold(g, E);
+          for (int g = 0; g < G; ++g) {
+            const R4 c0 = lcoef[wv][q * G + g];
+            R E[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(c0.x + xr[b] * (c0.y + xr[b] * c0.z));
+            fold(g, E);
+          }
+        } else {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            R E[B];
+            uniform_E(q * G + g, E);
+            fold(g, E);
+          }
         }
       } else {
 #pragma unroll
@@ -460,8 +490,21 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       if constexpr (UNI) {
         v += nl_uni * (Math<R>::log2_(mprod) + (R)esum);
       } else {
+        // one logarithm per bin; in single precision again on the mantissa
+        // alone: the hardware logarithm's bias is a fraction of the result's
+        // last place, which for log2 L of tens would add up coherently over
+        // the bins of a state
 #pragma unroll
-        for (int b = 0; b < B; ++b) v += NL[b] * Math<R>::log2_(Lm[b]);
+        for (int b = 0; b < B; ++b) {
+          if constexpr (kMixed) {
+            int e;
+            const R m = frexp(Lm[b], &e);
+            v += NL[b] * (Math<R>::log2_(m) + (R)e);
+            ok = ok && __builtin_isnormal(Lm[b]);
+          } else {
+            v += NL[b] * Math<R>::log2_(Lm[b]);
+          }
+        }
       }
       Acc acc = (Acc)v;
       if (!ok || !isfinite(acc)) {

@@ -298,8 +298,8 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
   const int klast = min(kbase + CH, K) - 1;
   const double xf = x64[kbase];
   const double xl = x64[klast];
-  // abscissa origin of the single-precision table rows (start of their 512-bin block)
-  const double xo = kMixed ? x64[(kbase / ref_chunk) * ref_chunk] : 0.0;
+  // abscissa origin of the single-precision table rows (midpoint of their 512-bin block)
+  const double xo = kMixed ? block_origin(x64, (kbase / ref_chunk) * ref_chunk, K) : 0.0;
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);

@@ -177,6 +177,16 @@ constexpr int kB32 = 8;                        // bins per lane, mixed kernel
 constexpr int kMergeBins = 4;
 constexpr int kChunk64 = kWave * kB64;         // 256 bins per wave
 constexpr int kChunk32 = kWave * kB32;         // 512 bins per wave
+
+// Origin of the single-precision abscissa row of the table block that starts
+// at bin kb (kChunk32 consecutive bins): the midpoint of the block's first and
+// last bin abscissae, so that |x - origin| is at most half the block's span.
+__host__ __device__ inline double block_origin(const double* x, int kb, int K) {
+  const int k0 = kb < K ? kb : K - 1;
+  const int k1 = kb + kChunk32 - 1 < K ? kb + kChunk32 - 1 : K - 1;
+  return 0.5 * (x[k0] + x[k1]);
+}
+
 constexpr int kPlainBlock = 256;
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include "lps_internal.hpp"
 #include "lps_spline.hpp"
 #include "lps_validate.hpp"
+#include "lps_roctx.hpp"
 
 namespace lps {
 namespace {
@@ -205,6 +206,7 @@ hipError_t launch_plain(lps_ctx* ctx, const lps_states* st, double* logL, uint32
 
 extern "C" lps_status lps_loglike_plain_fp64_noalloc(const lps_dataset_desc* d, const lps_states* st,
                                                      double* logL, uint32_t* status, void* stream) {
+  LPS_API_RANGE();
   if (!d || !st) return LPS_E_NULL;
   if (!d->f || !d->nk || !d->D || !d->R) return LPS_E_NULL;
   if (d->n_bins < 1 || d->n_spl < 0 || d->n_spl > 4) return LPS_E_SHAPE;

@@ -9,6 +9,7 @@
 // achieved lane-instruction rate of the device.
 #include "lps_internal.hpp"
 #include "lps_math64.hpp"
+#include "lps_roctx.hpp"
 
 namespace lps {
 namespace {
@@ -69,6 +70,7 @@ __global__ void k_math64(int n, int fn, const double* __restrict__ x, double* __
 }  // namespace lps
 
 extern "C" lps_status lps_math64_check(const double* x, int32_t n, int32_t fn, double* out, void* stream) {
+  LPS_API_RANGE();
   if (n == 0) return LPS_OK;
   if (!x || !out) return LPS_E_NULL;
   if (n < 0 || fn < 0 || fn > 4) return LPS_E_SHAPE;
@@ -79,6 +81,7 @@ extern "C" lps_status lps_math64_check(const double* x, int32_t n, int32_t fn, d
 
 extern "C" lps_status lps_valu_probe(int device, double* fma_ns_per_wave_instr, double* trans_over_fma,
                                      double* lane_instr_per_s) {
+  LPS_API_RANGE();
   if (!fma_ns_per_wave_instr || !trans_over_fma || !lane_instr_per_s) return LPS_E_NULL;
   if (hipSetDevice(device) != hipSuccess) return LPS_E_DEVICE;
   hipDeviceProp_t prop;

@@ -37,6 +37,7 @@
 
 #include "lps_internal.hpp"
 #include "lps_validate.hpp"
+#include "lps_roctx.hpp"
 
 namespace lps {
 
@@ -605,6 +606,7 @@ lps_states current_states(const lps_sampler* sm) {
 extern "C" {
 
 lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* d, lps_sampler** out) {
+  LPS_API_RANGE();
   if (!ctx || !d || !out || !d->betas) return LPS_E_NULL;
   *out = nullptr;
   if (d->n_walkers < 1 || d->n_temps < 1 || d->k_in_max < 0 || d->k_in_max + 2 > ctx->k_max) return LPS_E_SHAPE;
@@ -681,6 +683,7 @@ lps_status lps_sampler_create(lps_ctx* ctx, const lps_sampler_desc* d, lps_sampl
 }
 
 lps_status lps_sampler_destroy(lps_sampler* sm) {
+  LPS_API_RANGE();
   if (!sm) return LPS_OK;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {sm->cp,  sm->pp,  sm->off, sm->ccnt, sm->pcnt, sm->cx,  sm->cy,   sm->px,    sm->py,
@@ -693,6 +696,7 @@ lps_status lps_sampler_destroy(lps_sampler* sm) {
 }
 
 lps_status lps_sampler_set_state(lps_sampler* sm, const lps_states* init, uint64_t sweep_index, void* stream) {
+  LPS_API_RANGE();
   if (!sm || !init || !init->params || !init->knot_off || !init->knot_x || !init->knot_y) return LPS_E_NULL;
   if (init->n_states != sm->C || init->knot_cnt || init->n_knots < 0) return LPS_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
@@ -713,6 +717,7 @@ lps_status lps_sampler_set_state(lps_sampler* sm, const lps_states* init, uint64
 }
 
 lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
+  LPS_API_RANGE();
   if (!sm) return LPS_E_NULL;
   if (n_sweeps < 0) return LPS_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
@@ -748,6 +753,7 @@ lps_status lps_sampler_sweep(lps_sampler* sm, int32_t n_sweeps, void* stream) {
 
 lps_status lps_sampler_get_state(lps_sampler* sm, double* params, int32_t* knot_off, int32_t* knot_cnt,
                                  double* knot_x, double* knot_y, double* logL, uint64_t* sweep_index, void* stream) {
+  LPS_API_RANGE();
   if (!sm) return LPS_E_NULL;
   hipStream_t s = (hipStream_t)stream;
   const size_t C = sm->C, P = sm->P, NS = sm->NS, KC = sm->KC;
@@ -771,6 +777,7 @@ lps_status lps_sampler_get_state(lps_sampler* sm, double* params, int32_t* knot_
 }
 
 lps_status lps_sampler_counters(lps_sampler* sm, uint32_t* counters, void* stream) {
+  LPS_API_RANGE();
   if (!sm || !counters) return LPS_E_NULL;
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(counters, sm->counters, (size_t)lps::kKinds * sm->T * 2 * 4, hipMemcpyDeviceToHost, s) !=
@@ -781,6 +788,7 @@ lps_status lps_sampler_counters(lps_sampler* sm, uint32_t* counters, void* strea
 }
 
 lps_status lps_philox4x32_10(uint64_t seed, uint64_t first_counter, int32_t n, uint32_t* out, void* stream) {
+  LPS_API_RANGE();
   if (!out && n > 0) return LPS_E_NULL;
   if (n < 0) return LPS_E_SHAPE;
   if (n == 0) return LPS_OK;

@@ -49,7 +49,7 @@ __global__ void k_scaled(int K, int k_pad, int chunk, Layout lay, const double* 
   if (k < K) {
     double xk = x[k];
     int kc = (k / chunk) * chunk;           // first bin of this bin's wave chunk
-    row[0] = write32 ? (xk - x[kc < K ? kc : K - 1]) : xk;
+    row[0] = write32 ? (xk - block_origin(x, kc, K)) : xk;
     for (int term = 0; term < lay.n_terms; ++term)
       for (int c = 0; c < nch; ++c) {
         const int pc = (nch == 2 && c == 1) ? 2 : c;   // merged rows are (A = E, T)
@@ -68,7 +68,7 @@ __global__ void k_scaled(int K, int k_pad, int chunk, Layout lay, const double* 
   } else {
     // abscissa of the last bin keeps every spline piece finite on padding
     int kc = (k / chunk) * chunk;
-    row[0] = write32 ? (x[K - 1] - x[kc < K ? kc : K - 1]) : x[K - 1];
+    row[0] = write32 ? (x[K - 1] - block_origin(x, kc, K)) : x[K - 1];
     for (int r = 1; r < n_tab; ++r) row[r] = 1.0;
     for (int c = 0; c < nch; ++c) row[tab_nd(c, lay.n_terms, nch)] = 0.0;
     row[tab_nl(lay.n_terms, nch)] = 0.0;

@@ -14,7 +14,7 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from . import Context, Sampler, States
+from . import Context, Sampler, States, column_median
 
 
 @dataclass
@@ -70,17 +70,20 @@ def two_step(ctx: Context, n_walkers: int, betas, init_params: np.ndarray, k_in_
     sm1 = Sampler(ctx, n_walkers, betas, seed=seed, k_in_max=0, step=step, precision=precision, rj_moves=False)
     sm1.set_state(templates_only_states(ctx, np.ascontiguousarray(init_params, dtype=np.float64)))
     sm1.sweep(burn1)
-    draws, lls = [], []
-    for _ in range(keep1):
+    # the b = 1 rung's draws stay on the device ([P][keep1 * W] and [keep1 * W])
+    lo, hi = cold * n_walkers, (cold + 1) * n_walkers
+    rec_p = torch.empty((P, keep1 * n_walkers), dtype=torch.float64, device=ctx.device)
+    rec_l = torch.empty(keep1 * n_walkers, dtype=torch.float64, device=ctx.device)
+    for i in range(keep1):
         sm1.sweep(1)
-        s = sm1.get_state()
-        p = s["params"].cpu().numpy()[:, cold * n_walkers:(cold + 1) * n_walkers]
-        draws.append(p.T)
-        lls.append(s["logL"].cpu().numpy()[cold * n_walkers:(cold + 1) * n_walkers])
+        s = sm1.get_state(sweep_index=False)
+        rec_p[:, i * n_walkers:(i + 1) * n_walkers] = s["params"][:, lo:hi]
+        rec_l[i * n_walkers:(i + 1) * n_walkers] = s["logL"][lo:hi]
     sm1.close()
-    draws = np.concatenate(draws) if draws else np.zeros((0, P))
-    lls = np.concatenate(lls) if lls else np.zeros(0)
-    medians = np.median(draws, axis=0)
+    # medians by the library's column-median kernel; one host read at the end
+    medians = column_median(rec_p).cpu().numpy() if keep1 > 0 else np.full(P, np.nan)
+    draws = rec_p.cpu().numpy().T
+    lls = rec_l.cpu().numpy()
     # step 2: template parameters fixed at the medians, splines free
     sm2 = Sampler(ctx, n_walkers, betas, seed=seed + 1, k_in_max=k_in_max, step=step, precision=precision,
                   fixed_params=range(P), rj_moves=True)

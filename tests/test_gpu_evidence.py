@@ -90,3 +90,15 @@ def test_evidence_over_sampler_records_with_the_paper_ladder(lps):
     ref = E.dic(_by_rung(host)[T - 1], float(host[:, -1, :].mean()))
     for a, b in zip(got, ref):
         assert _close(a, b, abs_=1e-6)
+
+
+def test_column_median_matches_numpy(lps):
+    """lps_column_median (the step-1 summary of the two-step driver) against
+    numpy.median: odd and even counts, ties, a single value."""
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 7, 64, 1001, 4096):
+        x = rng.normal(size=(5, n))
+        x[1] = np.round(x[1] * 3) / 3           # many ties
+        x[2] = 4.25                              # all equal
+        got = lps.column_median(torch.as_tensor(x, device="cuda")).cpu().numpy()
+        np.testing.assert_array_equal(got, np.median(x, axis=1))

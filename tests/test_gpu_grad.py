@@ -173,3 +173,65 @@ def test_gradient_full_batch_sampled(lps):
             sy.append(dky[a:b])
         _compare(sub, ref, logL.cpu().numpy()[idx], dp[:, idx], torch.as_tensor(np.concatenate(sx)),
                  torch.as_tensor(np.concatenate(sy)), rel, f"{prec} full batch")
+
+
+def test_autograd_function_without_splines(lps):
+    """A layout with no spline slot at all (n_spl = 0): the template parameters
+    still get their gradients through LogLikeFn, and the knot inputs none."""
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=500, layout="split")
+    route = [[-1, -1, -1]] * 4
+    sb = W.make_states(name, ds, n_states=3, inbetween=(0, 0))
+    ctx = lps.Context(ds.f, ds.nk, D, ds.R, route, 0, max_states=sb.n, f_knee=ds.f_knee, arm_length=ds.arm_length)
+    params = torch.as_tensor(sb.params, device="cuda").clone().requires_grad_(True)
+    off = torch.zeros(1, dtype=torch.int32, device="cuda")
+    kx = torch.zeros(1, dtype=torch.float64, device="cuda", requires_grad=True)
+    ky = torch.zeros(1, dtype=torch.float64, device="cuda", requires_grad=True)
+    logL = lps.LogLikeFn.apply(ctx, "fp64", params, kx, ky, off)
+    logL.sum().backward()
+    none = [(np.zeros(0), np.zeros(0))] * 3
+    ds0 = W.Dataset(f=ds.f, nk=ds.nk, R=ds.R, Rfg=None, chi=ds.chi, truth=ds.truth, layout="split", n_spl=3,
+                    route=route)
+    for s in range(sb.n):
+        rl, rdp, _, _ = O.loglike_grad(ds0, D, sb.params[:, s], none)
+        assert abs(logL[s].item() - rl) <= 1e-9 * abs(rl)
+        scale = np.array([sb.params[0, s], sb.params[1, s], 1.0, 1.0])
+        g = params.grad[:, s].cpu().numpy() * scale
+        assert np.all(np.abs(g - rdp * scale) <= 1e-8 * (np.abs(rdp * scale).max() + 1.0)), (g, rdp)
+    assert kx.grad is None and ky.grad is None
+
+
+def test_mixed_adjoint_extreme_states_keep_fp64_status(lps):
+    """The adjoint's twin of the forward's extreme-state test: spline heights far
+    from zero push the per-bin products of channel PSDs, and beyond +-38 dex the
+    channel PSDs themselves, out of the single-precision range.  The mixed adjoint
+    re-evaluates such lanes in double range, so it must report the FP64 statuses,
+    and on the valid states logL and gradients must match the oracle (FP64 at
+    1e-8 of each family's largest component, mixed at 2e-4)."""
+    name = "grad_25000bins_1024states"
+    ds, D = C.dataset_with_data(name, n_bins=1500, layout="split")
+    shifts = [14.0, -14.0, 20.0, -20.0, 0.0, 11.0, 45.0, -45.0, 60.0, -60.0]
+    sb = W.make_states(name, ds, n_states=len(shifts), inbetween=(2, 6))
+    knots = [[(x.copy(), y.copy()) for (x, y) in C.knots_of(sb, s)] for s in range(sb.n)]
+    for s, shift in zip(range(sb.n), shifts):
+        x, y = knots[s][0]
+        knots[s][0] = (x, y + shift)        # OMS spline shifted by `shift` dex
+    ext = W.pack_states(sb.params.copy(), knots, 3)
+    ctx = C.make_context(lps, ds, D, max_states=ext.n)
+    st = C.device_states(ctx, ext)
+    _, s64 = ctx.loglike_batch(st, "fp64")
+    s64 = s64.cpu().numpy()
+    for prec in ("fp64", "mixed"):
+        status = ctx.loglike_grad_batch(st, prec)[4].cpu().numpy()
+        _say(prec, "adjoint status", status.tolist())
+        np.testing.assert_array_equal(status, s64)
+    valid = [s for s in range(ext.n) if s64[s] == 0]
+    assert len(valid) >= 6
+    sub = W.states_subset(ext, valid)
+    ctx_v = C.make_context(lps, ds, D, max_states=sub.n)
+    st_v = C.device_states(ctx_v, sub)
+    ref = _oracle_grads(ds, D, sub)
+    for prec, rel in (("fp64", 1e-8), ("mixed", 2e-4)):
+        logL, dp, dkx, dky, status = ctx_v.loglike_grad_batch(st_v, prec)
+        assert np.all(status.cpu().numpy() == 0)
+        _compare(sub, ref, logL.cpu().numpy(), dp, dkx, dky, rel, f"{prec} extreme states")

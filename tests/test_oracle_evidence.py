@@ -5,6 +5,7 @@ effective parameter count of a Gaussian posterior."""
 import math
 
 import numpy as np
+import pytest
 
 from oracle import evidence as E
 
@@ -116,3 +117,18 @@ def test_paper_ladder():
     for lo, hi in ((0, 5), (5, 15), (15, 20)):
         steps = np.diff(np.log10(b[lo:hi]))
         np.testing.assert_allclose(steps, steps[0], rtol=1e-9)
+
+
+def test_library_ladder_equals_the_pinned_oracle_ladder():
+    """The library's 20-rung ladder (lps_paper_ladder, a host function) is the
+    oracle's pinned ladder of Sec. "MCMC setup"."""
+    import os
+    lib_path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2507_06300_amd",
+                            "liblps.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("library not built")
+    import paper_2507_06300_amd as m
+    got = m.paper_ladder()
+    want = E.paper_ladder()
+    assert got.shape == (20,)
+    np.testing.assert_allclose(got, want, rtol=1e-15, atol=0)
