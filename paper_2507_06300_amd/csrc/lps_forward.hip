@@ -8,8 +8,10 @@
 // bin (binary search over the breakpoints), checks whether the next
 // breakpoint falls inside the chunk, and stages the piece's cubic (and, for a
 // crossing chunk, the next piece's) in LDS; ballots mark crossing and invalid
-// pairs.  For the single-precision path the cubic is re-expanded around the
-// start of the table block, so each bin's Horner runs on the stored abscissa.
+// pairs.  For the single-precision path each cubic is re-expanded in FP64
+// about an origin inside the stretch it covers (the table block's midpoint for
+// a piece that covers the whole chunk), so each bin's Horner runs on the stored
+// abscissa plus a small offset with well-conditioned coefficients.
 // Each bin then evaluates
 //   E_g = exp2(Q_g(x)),  S_c = sum of template rows times E_g  (Eq. (splines)),
 //   l   = sum_c N_k (D~_ck / S~_ck + ln S~_ck)
@@ -153,10 +155,14 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   constexpr bool kMixed = sizeof(R) == 4;
   // states whose pieces one wave locates at once (fewer for FP64 to bound LDS)
   constexpr int SUB = (kWave / G) < (kMixed ? 32 : 16) ? (kWave / G) : (kMixed ? 32 : 16);
-  // When a wave's chunk is a whole table block (its rows hold x - x_chunk), each
-  // piece's cubic is re-expanded around the chunk start once per sub-tile, and
-  // the per-bin Horner runs directly on the table abscissa.
-  constexpr bool kLocalPoly = kMixed && CH == kChunk32;
+  // Single precision: each staged piece's cubic is re-expanded in FP64 around
+  // an origin inside the stretch of the chunk that the piece covers (the table
+  // block's midpoint when the piece covers the whole chunk, else the chunk
+  // start or the piece's own start), so that the per-bin Horner runs on
+  // x - origin = (table abscissa) + (small offset) with well-conditioned
+  // coefficients: a short, steep piece expanded about a distant point would
+  // lose its value to cancellation.
+  constexpr bool kLocalPoly = kMixed;
   constexpr bool kScalars = FG || MODE != kSplit;
   // Per wave: the located piece of every (state, group) pair of the sub-tile
   // (a, b, c, d, offset), the per-state scalars, and the per-state lane
@@ -230,18 +236,19 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       // decides, and only a crossing chunk searches for its last piece
       const double b_next = pi0 + 1 < pni ? bx[pbase + pi0 + 1] : (double)INFINITY;
       pi1 = b_next <= xl ? count_le(bx + pbase, pni, xl) : pi0;
-      // record of piece i (breakpoint bi): cubic coefficients and abscissa offset
-      auto piece_rec = [&](int i, double bi, R4& r4, R& off) {
+      // record of piece i (breakpoint bi): cubic coefficients and abscissa
+      // offset (single precision: about origin org, offset xo - org)
+      auto piece_rec = [&](int i, double bi, double org, R4& r4, R& off) {
         if constexpr (kLocalPoly) {
-          // Q(x) = a + b t + c t^2 + d t^3, t = x - bi = t0 + dx  ->  polynomial in dx = x - xo
+          // Q(x) = a + b t + c t^2 + d t^3, t = x - bi = t0 + dx  ->  polynomial in dx = x - org
           const double* cf = coef64 + (pbase + i) * 4;
-          const double t0 = xo - bi;
+          const double t0 = org - bi;
           const double a = cf[0], b = cf[1], c = cf[2], d = cf[3];
           r4.x = (R)(a + t0 * (b + t0 * (c + t0 * d)));
           r4.y = (R)(b + t0 * (2.0 * c + 3.0 * d * t0));
           r4.z = (R)(c + 3.0 * d * t0);
           r4.w = (R)d;
-          off = 0;
+          off = (R)(xo - org);
         } else {
           const R* cf = coef + (pbase + i) * 4;
           r4.x = cf[0];
@@ -253,21 +260,24 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
       };
       R4 r4;
       R off;
-      piece_rec(pi0, bx[pbase + pi0], r4, off);
+      // a piece that covers the whole chunk is expanded about the block
+      // midpoint xo (offset 0); in a crossing chunk the first piece about the
+      // chunk start and the next one about its own start
+      piece_rec(pi0, bx[pbase + pi0], pi1 > pi0 ? xf : xo, r4, off);
       if constexpr (kLocalPoly) {
-        // the cubic term d dx^3 over the chunk, |dx| <= half the block span
+        // the cubic term d dx^3 over the chunk, |dx| <= h
         const double h = fmax(xl - xo, xo - xf);
         pquad = fabs(coef64[(pbase + pi0) * 4 + 3]) * h * h * h <= kQuadTol;
       }
       lcoef[wv][lane] = r4;
-      if constexpr (!kLocalPoly) loff[wv][lane] = off;
+      loff[wv][lane] = off;
       if (pi1 > pi0) {
         // the chunk crosses breakpoint pi0 + 1: stage the next piece as well,
         // with the abscissa (in the table's units) where it takes over
         const double b1 = b_next;
-        piece_rec(pi0 + 1, b1, r4, off);
+        piece_rec(pi0 + 1, b1, b1, r4, off);
         lcoef2[wv][lane] = r4;
-        if constexpr (!kLocalPoly) loff2[wv][lane] = off;
+        loff2[wv][lane] = off;
         llim[wv][lane] = kMixed ? (R)(b1 - xo) : (R)b1;
       }
     }
@@ -332,8 +342,10 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           if constexpr (MODE == kSplit) {
+            // the OMS row is 1 in this layout (the tables are scaled by it)
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) S[c][b] += Kt[g][c][b] * E[b];
+            for (int c = 0; c < NCH; ++c)
+              S[c][b] = g == 0 ? (FG ? S[c][b] + E[b] : E[b]) : S[c][b] + Kt[g][c][b] * E[b];
           } else if constexpr (MODE == kShared) {
             // OMS and TM share the noise exponent; their amplitudes weight the rows
 #pragma unroll
@@ -384,9 +396,14 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
             const size_t base = (size_t)(s * G + g) * kMaxKnots;
             for (int j = i0; j <= i1; ++j) {
               const R* cf = coef + (base + j) * 4;
-              const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
               const double bj = bx[base + j];
-              const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
+              // the first piece as staged (expanded about the chunk start); the
+              // later ones start inside the chunk and are used about their start
+              const bool first = kLocalPoly && j == i0;
+              const R4 c0 = lcoef[wv][pl];
+              const R a = first ? c0.x : cf[0], bb = first ? c0.y : cf[1];
+              const R cc = first ? c0.z : cf[2], dd = first ? c0.w : cf[3];
+              const R off = first ? loff[wv][pl] : (kMixed ? (R)(xo - bj) : (R)(-bj));
               const R lim = kMixed ? (R)(bj - xo) : (R)bj;   // bin is in piece j when xr >= lim
 #pragma unroll
               for (int b = 0; b < B; ++b) {
@@ -399,11 +416,8 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
             const R4 c0 = lcoef[wv][pl];
             const R4 c1 = lcoef2[wv][pl];
             const R lim = str ? llim[wv][pl] : (R)INFINITY;
-            R o0 = 0, o1 = 0;
-            if constexpr (!kLocalPoly) {
-              o0 = loff[wv][pl];
-              o1 = loff2[wv][pl];
-            }
+            const R o0 = loff[wv][pl];
+            const R o1 = str ? loff2[wv][pl] : o0;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
               const bool second = xr[b] >= lim;

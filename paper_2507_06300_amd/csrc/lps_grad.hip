@@ -130,8 +130,9 @@ __device__ inline T bin_score(int b, const R (&qx)[G], const R (&Kt)[NT][NCH][B]
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     if constexpr (MODE == kSplit) {
+      // the OMS row is 1 in this layout (the tables are scaled by it)
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) S[c] += (T)Kt[g][c][b] * e[g];
+      for (int c = 0; c < NCH; ++c) S[c] = g == 0 ? (FG ? S[c] + e[g] : e[g]) : S[c] + (T)Kt[g][c][b] * e[g];
     } else if constexpr (MODE == kShared) {
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
@@ -170,7 +171,7 @@ __device__ inline T bin_score(int b, const R (&qx)[G], const R (&Kt)[NT][NCH][B]
     if constexpr (MODE == kSplit) {
       T a = 0;
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) a += h[c] * (T)Kt[g][c][b];
+      for (int c = 0; c < NCH; ++c) a += g == 0 ? h[c] : h[c] * (T)Kt[g][c][b];
       gq[g] = a * e[g];
     } else {
       const bool noise = MODE == kShared ? g == 0 : g < 3;
@@ -241,7 +242,8 @@ template <typename R, int MODE, int NCH, bool FG, int B>
 __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_tiles, int tile, int K, int k_pad,
                                               int ref_chunk, const R* __restrict__ tab,
                                               const double* __restrict__ x64, const double* __restrict__ bx,
-                                              const R* __restrict__ coef, const int32_t* __restrict__ n_int,
+                                              const R* __restrict__ coef, const double* __restrict__ coef64,
+                                              const int32_t* __restrict__ n_int,
                                               const StateScalars* __restrict__ scal, R* __restrict__ rec,
                                               int2* __restrict__ gidx, double* __restrict__ glast,
                                               double* __restrict__ moments, double* __restrict__ lrec) {
@@ -257,8 +259,15 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
   // Per wave: the located piece of every (state, group) pair of the sub-tile
   // and, for a chunk that crosses the next breakpoint, that next piece and the
   // abscissa where it takes over (all in table units); per-state scalars.
+  // lc0/lc1 hold each piece's exponent cubic about an origin chosen as in the
+  // forward kernel (single precision: the block midpoint for a piece that
+  // covers the whole chunk, else the chunk start or the piece's own start;
+  // offsets lq0/lq1 = xo - origin), loff0/loff1 the offsets xo - x_piece of
+  // the piece-relative abscissa t that the moments use.
   __shared__ R4 lc0[kWavesPerBlock][kWave];
   __shared__ R4 lc1[kWavesPerBlock][kWave];
+  __shared__ R lq0[kWavesPerBlock][kWave];
+  __shared__ R lq1[kWavesPerBlock][kWave];
   __shared__ R loff0[kWavesPerBlock][kWave];
   __shared__ R loff1[kWavesPerBlock][kWave];
   __shared__ R llim[kWavesPerBlock][kWave];
@@ -314,21 +323,36 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
       const double b_next = pi0 + 1 < pni ? bx[pbase + pi0 + 1] : (double)INFINITY;
       pi1 = b_next <= xl ? count_le(bx + pbase, pni, xl) : pi0;
       const double b0 = bx[pbase + pi0];
-      const R* cf = coef + (pbase + pi0) * 4;
+      // exponent cubic of piece i (start bi) about origin org, and its offset
+      auto stage = [&](int i, double bi, double org, R4& r4, R& off) {
+        if constexpr (kMixed) {
+          const double* cf = coef64 + (pbase + i) * 4;
+          const double t0 = org - bi;
+          const double a = cf[0], b = cf[1], c = cf[2], d = cf[3];
+          r4.x = (R)(a + t0 * (b + t0 * (c + t0 * d)));
+          r4.y = (R)(b + t0 * (2.0 * c + 3.0 * d * t0));
+          r4.z = (R)(c + 3.0 * d * t0);
+          r4.w = (R)d;
+          off = (R)(xo - org);
+        } else {
+          const R* cf = coef + (pbase + i) * 4;
+          r4.x = cf[0];
+          r4.y = cf[1];
+          r4.z = cf[2];
+          r4.w = cf[3];
+          off = (R)(-bi);
+        }
+      };
       R4 r4;
-      r4.x = cf[0];
-      r4.y = cf[1];
-      r4.z = cf[2];
-      r4.w = cf[3];
+      R qo;
+      stage(pi0, b0, pi1 > pi0 ? xf : xo, r4, qo);
       lc0[wv][lane] = r4;
+      lq0[wv][lane] = qo;
       loff0[wv][lane] = kMixed ? (R)(xo - b0) : (R)(-b0);
       if (pi1 > pi0) {
-        const R* cf1 = coef + (pbase + pi0 + 1) * 4;
-        r4.x = cf1[0];
-        r4.y = cf1[1];
-        r4.z = cf1[2];
-        r4.w = cf1[3];
+        stage(pi0 + 1, b_next, b_next, r4, qo);
         lc1[wv][lane] = r4;
+        lq1[wv][lane] = qo;
         loff1[wv][lane] = kMixed ? (R)(xo - b_next) : (R)(-b_next);
         llim[wv][lane] = kMixed ? (R)(b_next - xo) : (R)b_next;
       }
@@ -375,7 +399,9 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             T[g][b] = xr[b] + o0;
-            Qe[g][b] = c0.x + T[g][b] * (c0.y + T[g][b] * (c0.z + T[g][b] * c0.w));
+            // single precision: the cubic about the block midpoint (offset 0)
+            const R tq = kMixed ? xr[b] : T[g][b];
+            Qe[g][b] = c0.x + tq * (c0.y + tq * (c0.z + tq * c0.w));
           }
         }
       } else {
@@ -384,17 +410,19 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
           const int pl = q * G + g;
           if (!((multi >> pl) & 1ull)) {   // at most one breakpoint: both staged pieces from LDS
             const R4 c0 = lc0[wv][pl];
-            const R o0 = loff0[wv][pl];
+            const R o0 = loff0[wv][pl], d0 = lq0[wv][pl];
             const bool str = (straddle >> pl) & 1ull;
             const R4 c1 = str ? lc1[wv][pl] : c0;
             const R o1 = str ? loff1[wv][pl] : o0;
+            const R d1 = str ? lq1[wv][pl] : d0;
             const R lim = str ? llim[wv][pl] : (R)INFINITY;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
               const bool second = xr[b] >= lim;
               const R4 cc = second ? c1 : c0;
               T[g][b] = xr[b] + (second ? o1 : o0);
-              Qe[g][b] = cc.x + T[g][b] * (cc.y + T[g][b] * (cc.z + T[g][b] * cc.w));
+              const R tq = xr[b] + (second ? d1 : d0);
+              Qe[g][b] = cc.x + tq * (cc.y + tq * (cc.z + tq * cc.w));
             }
           } else {         // several breakpoints: each piece from memory, select per bin
             const int i0 = __builtin_amdgcn_readlane(pi0, pl);
@@ -403,14 +431,21 @@ __global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_
             R Q[B] = {};
             for (int j = i0; j <= i1; ++j) {
               const R* cf = coef + (base + j) * 4;
-              const R a = cf[0], bb = cf[1], cc = cf[2], dd = cf[3];
               const double bj = bx[base + j];
+              // the first piece as staged (about the chunk start in single
+              // precision); the later ones start inside the chunk
+              const bool first = kMixed && j == i0;
+              const R4 c0 = lc0[wv][pl];
+              const R a = first ? c0.x : cf[0], bb = first ? c0.y : cf[1];
+              const R cc = first ? c0.z : cf[2], dd = first ? c0.w : cf[3];
               const R off = kMixed ? (R)(xo - bj) : (R)(-bj);
+              const R qoff = first ? lq0[wv][pl] : off;
               const R lim = kMixed ? (R)(bj - xo) : (R)bj;
 #pragma unroll
               for (int b = 0; b < B; ++b) {
                 const R tt = xr[b] + off;
-                const R qv = a + tt * (bb + tt * (cc + tt * dd));
+                const R tq = xr[b] + qoff;
+                const R qv = a + tq * (bb + tq * (cc + tq * dd));
                 const bool sel = (j == i0) || (xr[b] >= lim);
                 Q[b] = sel ? qv : Q[b];
                 T[g][b] = sel ? tt : T[g][b];
@@ -761,7 +796,8 @@ hipError_t dispatch_grad(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int til
   const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
 #define LPS_GRAD(MODE, NCH, FG)                                                                            \
   hipLaunchKernelGGL((k_grad<R, MODE, NCH, FG, B>), grid, block, 0, s, n, n_chunks, n_tiles, tile,       \
-                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->n_int, ctx->scal, rec, \
+                     ctx->n_bins, k_pad, kChunk32, tab, ctx->x, ctx->bx, coef, ctx->coef64, ctx->n_int,       \
+                     ctx->scal, rec,                                                                          \
                      gidx, glast, ctx->moments, lrec)
   const bool fg = L.has_fg != 0;
   if (L.mode == kSplit && L.nch == 2 && !fg) LPS_GRAD(kSplit, 2, false);

@@ -13,7 +13,11 @@
 //
 // Per-bin tables are scaled by a reference PSD sigma_c(f_k) (the noise
 // template at reference amplitudes) so that every single-precision quantity
-// is O(1); the constant C0 = -sum N_k ln sigma_ck is kept in double.
+// is O(1); the constant C0 = -sum N_k ln sigma_ck is kept in double.  In the
+// split layout sigma_c is the OMS term alone (at the reference amplitude), so
+// that the OMS row is exactly 1 and the kernels add the OMS group's factor
+// without a product; its ratio to the whole noise stays below about 110 over
+// the analysis band (the TM term dominates A and E only below a few mHz).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,6 +61,10 @@ struct Layout {
   int n_terms;                   // terms with a table: OMS, TM, SGWB (+FG)
   int n_tab;                     // per-bin table rows
 };
+
+// True when the scaled OMS row is exactly 1 (split layout: the tables are
+// scaled by the OMS reference term, see the top of this file).
+__host__ __device__ inline bool unit_oms_row(const Layout& L) { return L.mode == kSplit; }
 
 // Per-bin table rows (same order in the FP64 and FP32 tables):
 //   row 0                     : x (FP64 table) or x - x_chunk (FP32 table)

@@ -15,7 +15,7 @@ namespace lps {
 namespace {
 
 __global__ void k_templates(int K, const double* __restrict__ f, double L, const double* __restrict__ R,
-                            const double* __restrict__ Rfg, double* __restrict__ x,
+                            const double* __restrict__ Rfg, int unit_oms, double* __restrict__ x,
                             double* __restrict__ tmpl, double* __restrict__ sigma) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
@@ -30,7 +30,9 @@ __global__ void k_templates(int K, const double* __restrict__ f, double L, const
     tmpl[(1 * 3 + c) * (size_t)K + k] = tm[c];
     tmpl[(2 * 3 + c) * (size_t)K + k] = R[c * (size_t)K + k] * h;
     tmpl[(3 * 3 + c) * (size_t)K + k] = Rfg ? Rfg[c * (size_t)K + k] : 0.0;
-    sigma[c * (size_t)K + k] = kRefAoms * kRefAoms * oms[c] + kRefAtm * kRefAtm * tm[c];
+    // the OMS row of the scaled table is then ref * oms / (ref * oms) = 1 exactly
+    sigma[c * (size_t)K + k] = unit_oms ? kRefAoms * kRefAoms * oms[c]
+                                        : kRefAoms * kRefAoms * oms[c] + kRefAtm * kRefAtm * tm[c];
   }
 }
 
@@ -105,7 +107,7 @@ hipError_t build_tables(lps_ctx* ctx, hipStream_t s) {
   const int K = ctx->n_bins;
   const int tpb = 256;
   hipLaunchKernelGGL(k_templates, dim3((K + tpb - 1) / tpb), dim3(tpb), 0, s, K, ctx->f, ctx->arm_length,
-                     ctx->R, ctx->Rfg, ctx->x, ctx->tmpl, ctx->sigma);
+                     ctx->R, ctx->Rfg, unit_oms_row(ctx->lay) ? 1 : 0, ctx->x, ctx->tmpl, ctx->sigma);
   hipLaunchKernelGGL(k_scaled, dim3((ctx->k_pad64 + tpb - 1) / tpb), dim3(tpb), 0, s, K, ctx->k_pad64, kChunk64,
                      ctx->lay, ctx->x, ctx->nk, ctx->D, ctx->tmpl, ctx->sigma, ctx->tab64, (float*)nullptr, 0);
   hipLaunchKernelGGL(k_scaled, dim3((ctx->k_pad32 + tpb - 1) / tpb), dim3(tpb), 0, s, K, ctx->k_pad32, kChunk32,

@@ -42,18 +42,71 @@ def device_states(ctx, sb):
     return ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
 
 
-def mixed_tolerance(ds, D, sb, idx):
-    """Derived bound for the mixed path.
+EPS32 = 2.0 ** -24
 
-    Each per-bin term N_k (D/S + ln S~) is formed from single-precision
-    operations whose combined relative error is a few tens of units of
-    2^-24; with eps = 2^-24 and a budget of 32 eps per term, the bound is
-    32 eps * sum_ck N_k (D_ck/S_ck + |ln S_ck / sigma| + 1) where the log of the
-    scaled PSD is bounded by 8 over the prior box.
-    """
-    eps = 2.0 ** -24
-    out = []
+# FP64 paths: |dlogL| <= FP64_REL * sum_ck N_k (D_ck/S_ck + |ln S_ck|), the sum
+# of the magnitudes of the summed terms (the condition of the sum; for every
+# state here it is within a few per cent of |logL|).  Each term is a handful
+# of correctly rounded FP64 operations, so the error is a few units of 2^-53
+# of it; measured: at most 3e-15.
+FP64_REL = 1e-13
+
+# Mixed path: each term N_k (D/S + ln S~) is formed in single precision from
+# S~ = sum_g K~_g 2^Q_g (S~ = S / sigma, sigma the nominal noise level).  The
+# relative error of S~ is a few units of 2^-24 plus the rounding of the
+# exponent, about |Q| 2^-24 ln 2 with |Q| ~ |log2 S~|; D/S inherits it plus a
+# few roundings (reciprocal, products of the merged fraction), and ln S~ takes
+# it as an absolute error (the logarithm of the mantissa adds a fixed amount).
+# Per term the error is therefore at most of order
+#   eps N_k (D/S + 1) (1 + |ln S~|),
+# and the bound is MIXED_C times its sum over bins and channels.  MIXED_C is
+# the worst measured ratio with a margin of almost three: 1.4, on a state of
+# the one-year workload in the paper's layout whose PSD is 1e5 below the data;
+# at most 0.6 on every other case here, extreme and full-size ones included.
+MIXED_C = 4.0
+
+
+def _nominal_sigma(ds):
+    """Noise PSD per channel at the centre of the Table I priors (15 pm, 3 fm)."""
+    oms, tm = O.noise_tdi(ds.f, ds.arm_length, 15e-12, 3e-15)
+    return oms + tm
+
+
+def term_magnitudes(ds, D, sb, idx):
+    """Per state: (sum N (D/S + |ln S|), sum N (D/S + 1)(1 + |ln S/sigma|))."""
+    sig = _nominal_sigma(ds)
+    N = ds.nk[None, :]
+    a64, a32 = [], []
     for s in idx:
         S, _, _ = O.psd(ds, sb.params[:, s], knots_of(sb, s))
-        out.append(32 * eps * math.fsum((ds.nk[None, :] * (D / S + 9.0)).ravel()))
-    return np.array(out)
+        r = D / S
+        a64.append(math.fsum((N * (r + np.abs(np.log(S)))).ravel()))
+        a32.append(math.fsum((N * (r + 1.0) * (1.0 + np.abs(np.log(S / sig)))).ravel()))
+    return np.array(a64), np.array(a32)
+
+
+def fp64_tolerance(ds, D, sb, idx):
+    return FP64_REL * term_magnitudes(ds, D, sb, idx)[0]
+
+
+def mixed_tolerance(ds, D, sb, idx):
+    """The mixed path's bound MIXED_C eps sum_ck N_k (D/S + 1)(1 + |ln S~|)."""
+    return MIXED_C * EPS32 * term_magnitudes(ds, D, sb, idx)[1]
+
+
+# Bias check: the median over a batch of states of the signed mixed-path
+# error.  The error model's only terms of one sign in every state are the
+# mean roundings of the hardware reciprocal, exponential and logarithm (each
+# well below 0.2 eps per term), at most 0.2 eps sum N (D/S + 1) per state: below
+# 0.15 nats for every case here.  A median above MIXED_BIAS therefore means a
+# bias common to the states (a dropped term, a wrong constant), which a
+# per-state bound that grows with N K could let through.
+MIXED_BIAS = 0.5
+
+
+def check_mixed(got, ref, tol, label=""):
+    """Mixed results within the per-state bound, and no bias common to the states."""
+    err = np.asarray(got) - np.asarray(ref)
+    assert np.all(np.abs(err) <= tol), (label, np.abs(err).max(), (np.abs(err) / tol).max())
+    assert abs(np.median(err)) <= MIXED_BIAS, (label, "median signed error", np.median(err))
+    return (np.abs(err) / tol).max()

@@ -95,8 +95,11 @@ def test_time_series_to_loglike_end_to_end(lps):
     st = ctx.states(sb.params, sb.knot_off, sb.knot_x, sb.knot_y)
     got64 = ctx.loglike_batch(st, "fp64")[0].cpu().numpy()
     gotm = ctx.loglike_batch(st, "mixed")[0].cpu().numpy()
-    assert np.all(np.abs(got64 - want) <= 1e-9 * np.abs(want)), (got64, want)
-    assert np.all(np.abs(gotm - want) <= C.mixed_tolerance(ds_o, D_r, sb, range(sb.n)))
+    # the device's data and the numpy data come from different FFTs (they agree
+    # to about 1e-12), so the FP64 bound adds that to the evaluation's own
+    tol64 = C.fp64_tolerance(ds_o, D_r, sb, range(sb.n)) + 1e-11 * np.abs(want)
+    assert np.all(np.abs(got64 - want) <= tol64), (got64, want)
+    assert np.all(np.abs(gotm - want) <= C.mixed_tolerance(ds_o, D_r, sb, range(sb.n)) + 1e-11 * np.abs(want))
 
 
 def test_planned_periodogram_matches_oracle_and_replays_from_a_graph(lps):

@@ -49,17 +49,20 @@ def test_year_workload_sampled_parity():
     ref = C.oracle_loglikes(ds, D, sb, sample)
     ref_st = C.oracle_status(ds, sb, sample)
     tol = C.mixed_tolerance(ds, D, sb, sample)
+    tol64 = C.fp64_tolerance(ds, D, sb, sample)
     for i, s in enumerate(sample):
         if not np.isfinite(ref[i]):
             assert not np.isfinite(l64[s])
             continue
         assert s64[s] == ref_st[i] and sm[s] == ref_st[i]
-        assert abs(l64[s] - ref[i]) <= 1e-9 * abs(ref[i]), (s, l64[s], ref[i])
+        assert abs(l64[s] - ref[i]) <= tol64[i], (s, l64[s], ref[i])
         assert abs(lm[s] - ref[i]) <= tol[i], (s, lm[s], ref[i], tol[i])
     # properties over every state: FP64 and mixed agree on the status of every
-    # state; mixed within single-precision distance of FP64 for all valid states
+    # state; mixed within 1e-7 of FP64 relative to logL for all valid states
+    # (the sampled states above carry the derived bound; 1e-7 is five times
+    # the largest relative difference measured over the 4,096 states)
     np.testing.assert_array_equal(sm, s64)
     ok = np.isfinite(l64)
     assert np.array_equal(ok, np.isfinite(lm))
     assert ok.sum() >= sb.n - 8
-    assert np.all(np.abs(lm[ok] - l64[ok]) <= 1e-6 * np.abs(l64[ok]))
+    assert np.all(np.abs(lm[ok] - l64[ok]) <= 1e-7 * np.abs(l64[ok]))

@@ -1,8 +1,12 @@
 """GPU parity of the adjoint: dlogL/d(params, knot heights, knot positions) vs the FP64 oracle.
 
-FP64 adjoint: |dg| <= 1e-8 * (||g_family||_inf + tiny) per family (params, heights, positions)
-mixed adjoint: |dg| <= 2e-4 * ||g_family||_inf (single-precision per-bin scores and moments)
+FP64 adjoint: |dg| <= 1e-12 * (||g_family||_inf + 1) per family (params, heights, positions)
+mixed adjoint: |dg| <= 2e-5 * (||g_family||_inf + 1) (single-precision per-bin scores and moments;
+the worst measured error is about 3e-6 of the family's largest component, on extreme states)
+logL of either adjoint: the forward's bounds (tests/cases.fp64_tolerance, mixed_tolerance)
 """
+FP64_GRAD = 1e-12
+MIXED_GRAD = 2e-5
 import sys
 
 import numpy as np
@@ -57,13 +61,14 @@ def _unpack(sb, dkx, dky):
     return res
 
 
-def _compare(sb, ref, logL, dp, dkx, dky, rel, label):
+def _compare(sb, ref, logL, dp, dkx, dky, rel, label, ltol):
+    """Gradients within rel of each family's largest component, logL within ltol[s]."""
     dp = dp.cpu().numpy()
     per = _unpack(sb, dkx.cpu().numpy(), dky.cpu().numpy())
     worst = 0.0
     for s in range(sb.n):
         rl, rdp, rdy, rdx = ref[s]
-        assert abs(logL[s] - rl) <= (1e-9 if rel < 1e-6 else 1e-6) * abs(rl)
+        assert abs(logL[s] - rl) <= ltol[s], (label, s, logL[s], rl, ltol[s])
         # template parameters: compare the dimensionless sensitivities theta * dlogL/dtheta
         scale = np.array([sb.params[0, s], sb.params[1, s], 1.0, 1.0, 1.0][:dp.shape[0]])
         a, b = dp[:, s] * scale, rdp * scale
@@ -95,12 +100,14 @@ def test_gradient_matches_oracle(lps, case):
     ref = _oracle_grads(ds, D, sb)
     logL, dp, dkx, dky, status = ctx.loglike_grad_batch(st, "fp64")
     assert np.all(status.cpu().numpy() == 0)
-    _compare(sb, ref, logL.cpu().numpy(), dp, dkx, dky, 1e-8, "fp64")
+    _compare(sb, ref, logL.cpu().numpy(), dp, dkx, dky, FP64_GRAD, "fp64", C.fp64_tolerance(ds, D, sb, range(sb.n)))
     f64 = ctx.loglike_batch(st, "fp64")[0].cpu().numpy()
     assert np.all(np.abs(logL.cpu().numpy() - f64) <= 1e-12 * np.abs(f64))
     logL, dp, dkx, dky, status = ctx.loglike_grad_batch(st, "mixed")
     assert np.all(status.cpu().numpy() == 0)
-    _compare(sb, ref, logL.cpu().numpy(), dp, dkx, dky, 2e-4, "mixed")
+    mtol = C.mixed_tolerance(ds, D, sb, range(sb.n))
+    _compare(sb, ref, logL.cpu().numpy(), dp, dkx, dky, MIXED_GRAD, "mixed", mtol)
+    C.check_mixed(logL.cpu().numpy(), np.array([r[0] for r in ref]), mtol, "mixed adjoint " + layout)
 
 
 def test_gradient_invalid_states_and_determinism(lps):
@@ -162,7 +169,8 @@ def test_gradient_full_batch_sampled(lps):
     idx = sorted({0, 1, 2, 13, 22, 40, sb.n - 1} | set(rng.choice(sb.n, 5, replace=False).tolist()))
     sub = W.states_subset(sb, idx)
     ref = _oracle_grads(ds, D, sub)
-    for prec, rel in (("fp64", 1e-8), ("mixed", 2e-4)):
+    tols = {"fp64": C.fp64_tolerance(ds, D, sub, range(sub.n)), "mixed": C.mixed_tolerance(ds, D, sub, range(sub.n))}
+    for prec, rel in (("fp64", FP64_GRAD), ("mixed", MIXED_GRAD)):
         logL, dp, dkx, dky, status = ctx.loglike_grad_batch(st, prec)
         assert np.all(status.cpu().numpy() == 0)
         dkx, dky = dkx.cpu().numpy(), dky.cpu().numpy()
@@ -172,7 +180,7 @@ def test_gradient_full_batch_sampled(lps):
             sx.append(dkx[a:b])
             sy.append(dky[a:b])
         _compare(sub, ref, logL.cpu().numpy()[idx], dp[:, idx], torch.as_tensor(np.concatenate(sx)),
-                 torch.as_tensor(np.concatenate(sy)), rel, f"{prec} full batch")
+                 torch.as_tensor(np.concatenate(sy)), rel, f"{prec} full batch", tols[prec])
 
 
 def test_autograd_function_without_splines(lps):
@@ -194,10 +202,10 @@ def test_autograd_function_without_splines(lps):
                     route=route)
     for s in range(sb.n):
         rl, rdp, _, _ = O.loglike_grad(ds0, D, sb.params[:, s], none)
-        assert abs(logL[s].item() - rl) <= 1e-9 * abs(rl)
+        assert abs(logL[s].item() - rl) <= 1e-13 * abs(rl)
         scale = np.array([sb.params[0, s], sb.params[1, s], 1.0, 1.0])
         g = params.grad[:, s].cpu().numpy() * scale
-        assert np.all(np.abs(g - rdp * scale) <= 1e-8 * (np.abs(rdp * scale).max() + 1.0)), (g, rdp)
+        assert np.all(np.abs(g - rdp * scale) <= FP64_GRAD * (np.abs(rdp * scale).max() + 1.0)), (g, rdp)
     assert kx.grad is None and ky.grad is None
 
 
@@ -207,7 +215,7 @@ def test_mixed_adjoint_extreme_states_keep_fp64_status(lps):
     channel PSDs themselves, out of the single-precision range.  The mixed adjoint
     re-evaluates such lanes in double range, so it must report the FP64 statuses,
     and on the valid states logL and gradients must match the oracle (FP64 at
-    1e-8 of each family's largest component, mixed at 2e-4)."""
+    1e-12 of each family's largest component, mixed at 2e-5)."""
     name = "grad_25000bins_1024states"
     ds, D = C.dataset_with_data(name, n_bins=1500, layout="split")
     shifts = [14.0, -14.0, 20.0, -20.0, 0.0, 11.0, 45.0, -45.0, 60.0, -60.0]
@@ -231,7 +239,8 @@ def test_mixed_adjoint_extreme_states_keep_fp64_status(lps):
     ctx_v = C.make_context(lps, ds, D, max_states=sub.n)
     st_v = C.device_states(ctx_v, sub)
     ref = _oracle_grads(ds, D, sub)
-    for prec, rel in (("fp64", 1e-8), ("mixed", 2e-4)):
+    tols = {"fp64": C.fp64_tolerance(ds, D, sub, range(sub.n)), "mixed": C.mixed_tolerance(ds, D, sub, range(sub.n))}
+    for prec, rel in (("fp64", FP64_GRAD), ("mixed", MIXED_GRAD)):
         logL, dp, dkx, dky, status = ctx_v.loglike_grad_batch(st_v, prec)
         assert np.all(status.cpu().numpy() == 0)
-        _compare(sub, ref, logL.cpu().numpy(), dp, dkx, dky, rel, f"{prec} extreme states")
+        _compare(sub, ref, logL.cpu().numpy(), dp, dkx, dky, rel, f"{prec} extreme states", tols[prec])

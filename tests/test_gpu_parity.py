@@ -1,7 +1,8 @@
 """GPU parity: HIP path vs the FP64 oracle on the same seeded inputs.
 
-FP64 paths:   |dlogL| <= 1e-9 |logL|          (the stated FP64 tolerance)
-mixed path:   |dlogL| <= derived bound          (tests/cases.mixed_tolerance)
+FP64 paths:   |dlogL| <= 1e-13 sum_ck N_k (D/S + |ln S|)   (tests/cases.fp64_tolerance)
+mixed path:   |dlogL| <= 4 eps sum_ck N_k (D/S + 1)(1 + |ln S~|)   (tests/cases.mixed_tolerance),
+              and a bound below one nat on most states, so that a 1-nat bias fails
 psd_build:    elementwise relative 1e-12
 status words: bit-exact
 """
@@ -60,14 +61,13 @@ def test_fp64_batched_and_plain_match_oracle(lps, case):
     got, status = ctx.loglike_batch(st, "fp64")
     got = got.cpu().numpy()
     assert np.all(status.cpu().numpy() == 0)
-    rel = np.abs(got - ref) / np.abs(ref)
-    _say("fp64 batched max rel err", rel.max())
-    assert rel.max() <= 1e-9
+    tol = C.fp64_tolerance(ds, D, sb, range(sb.n))
+    _say("fp64 batched max rel err", (np.abs(got - ref) / np.abs(ref)).max(), "of bound", (np.abs(got - ref) / tol).max())
+    assert np.all(np.abs(got - ref) <= tol)
     plain, pst = ctx.loglike_plain_fp64(st)
     plain = plain.cpu().numpy()
-    relp = np.abs(plain - ref) / np.abs(ref)
-    _say("plain fp64 max rel err", relp.max())
-    assert relp.max() <= 1e-9
+    _say("plain fp64 max rel err", (np.abs(plain - ref) / np.abs(ref)).max(), "of bound", (np.abs(plain - ref) / tol).max())
+    assert np.all(np.abs(plain - ref) <= tol)
     assert np.all(pst.cpu().numpy() == 0)
 
 
@@ -83,8 +83,8 @@ def test_mixed_matches_oracle_within_derived_bound(lps, case):
     assert np.all(status.cpu().numpy() == 0)
     err = np.abs(got - ref)
     tol = C.mixed_tolerance(ds, D, sb, range(sb.n))
-    _say("mixed max abs err", err.max(), "max rel", (err / np.abs(ref)).max(), "min tol", tol.min())
-    assert np.all(err <= tol)
+    _say("mixed max abs err", err.max(), "max rel", (err / np.abs(ref)).max(), "median tol", np.median(tol))
+    _say("mixed worst error / bound", C.check_mixed(got, ref, tol, case))
     # differences between states (what a Metropolis step uses)
     d_got = got[1:] - got[0]
     d_ref = ref[1:] - ref[0]
@@ -147,9 +147,10 @@ def test_knot_count_edge_cases(lps):
     got64 = ctx.loglike_batch(st, "fp64")[0].cpu().numpy()
     gotm = ctx.loglike_batch(st, "mixed")[0].cpu().numpy()
     gotp = ctx.loglike_plain_fp64(st)[0].cpu().numpy()
-    assert np.all(np.abs(got64 - ref) <= 1e-9 * np.abs(ref))
-    assert np.all(np.abs(gotp - ref) <= 1e-9 * np.abs(ref))
-    assert np.all(np.abs(gotm - ref) <= C.mixed_tolerance(ds, D, sb, range(sb.n)))
+    tol64 = C.fp64_tolerance(ds, D, sb, range(sb.n))
+    assert np.all(np.abs(got64 - ref) <= tol64)
+    assert np.all(np.abs(gotp - ref) <= tol64)
+    C.check_mixed(gotm, ref, C.mixed_tolerance(ds, D, sb, range(sb.n)), "knot counts")
 
 
 def test_invalid_states_status_and_minus_inf(lps):
@@ -175,13 +176,15 @@ def test_invalid_states_status_and_minus_inf(lps):
     st = C.device_states(ctx, bad)
     ref_status = C.oracle_status(ds, bad)
     ref = C.oracle_loglikes(ds, D, bad)
+    ok = ref_status == 0
+    good = [s for s in range(bad.n) if ok[s]]
+    tols = {"fp64": C.fp64_tolerance(ds, D, bad, good), "mixed": C.mixed_tolerance(ds, D, bad, good)}
     for prec in ("fp64", "mixed"):
         logL, status = ctx.loglike_batch(st, prec)
         np.testing.assert_array_equal(status.cpu().numpy(), ref_status)
         got = logL.cpu().numpy()
         assert np.all(np.isneginf(got[ref_status != 0]))
-        ok = ref_status == 0
-        assert np.all(np.abs(got[ok] - ref[ok]) <= np.abs(ref[ok]) * (1e-9 if prec == "fp64" else 1e-6))
+        assert np.all(np.abs(got[ok] - ref[ok]) <= tols[prec])
     plain, pst = ctx.loglike_plain_fp64(st)
     np.testing.assert_array_equal(pst.cpu().numpy(), ref_status)
     assert np.all(np.isneginf(plain.cpu().numpy()[ref_status != 0]))
@@ -239,7 +242,8 @@ def test_mixed_extreme_states_keep_fp64_status(lps):
     """Spline heights far from zero push the per-bin product of channel PSDs, and
     beyond +-38 dex the channel PSDs themselves, out of the single-precision
     range; the mixed path must still agree with FP64 on which states are valid
-    and on their logL (relative 1e-6), in every mixed launch shape."""
+    and on their logL (the oracle within the bounds of tests/cases), in every
+    mixed launch shape."""
     name = "grad_25000bins_1024states"
     ds, D = C.dataset_with_data(name, n_bins=2100, layout="split")
     shifts = [14.0, -14.0, 20.0, -20.0, 0.0, 11.0, 45.0, -45.0, 60.0, -60.0]
@@ -254,14 +258,17 @@ def test_mixed_extreme_states_keep_fp64_status(lps):
     l64, s64 = ctx.loglike_batch(st, "fp64")
     a = l64.cpu().numpy()
     ok = np.isfinite(a)
+    good = [s for s in range(ext.n) if ok[s]]
+    ref = C.oracle_loglikes(ds, D, ext)
+    assert np.all(np.abs(a[ok] - ref[ok]) <= C.fp64_tolerance(ds, D, ext, good))
+    tol = C.mixed_tolerance(ds, D, ext, good)
     for b, t in [(8, 0), (4, 0), (4, 3)]:
         ctx.set_launch("mixed", b, t)
         lmx, smx = ctx.loglike_batch(st, "mixed")
         np.testing.assert_array_equal(s64.cpu().numpy(), smx.cpu().numpy())
         bm = lmx.cpu().numpy()
-        assert np.all(np.abs(a[ok] - bm[ok]) <= 1e-6 * np.abs(a[ok])), (b, t)
-    ref = C.oracle_loglikes(ds, D, ext)
-    assert np.all(np.abs(a[ok] - ref[ok]) <= 1e-9 * np.abs(ref[ok]))
+        _say("extreme states", (b, t), "worst error / bound", (np.abs(bm[ok] - ref[ok]) / tol).max())
+        assert np.all(np.abs(bm[ok] - ref[ok]) <= tol), (b, t)
 
 
 @pytest.mark.parametrize("prec,shapes", [("fp64", [(2, 0), (4, 0), (2, 7), (4, 64)]),
@@ -273,7 +280,7 @@ def test_every_launch_shape_matches_oracle(lps, prec, shapes):
     ctx = C.make_context(lps, ds, D, max_states=sb.n)
     st = C.device_states(ctx, sb)
     ref = C.oracle_loglikes(ds, D, sb)
-    tol = 1e-9 * np.abs(ref) if prec == "fp64" else C.mixed_tolerance(ds, D, sb, range(sb.n))
+    tol = (C.fp64_tolerance if prec == "fp64" else C.mixed_tolerance)(ds, D, sb, range(sb.n))
     first = None
     for b, t in shapes:
         ctx.set_launch(prec, b, t)
