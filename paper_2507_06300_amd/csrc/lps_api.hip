@@ -362,7 +362,10 @@ lps_status lps_autotune(lps_ctx* ctx, const lps_states* st, lps_precision prec, 
   double* logL = nullptr;
   if (hipMalloc((void**)&logL, (size_t)n * sizeof(double)) != hipSuccess) return LPS_E_NOMEM;
   const int bpl[2][2] = {{4, 2}, {8, 4}};   // default first
-  const int tiles[] = {0, 16, 32, 64, 128, 256};
+  // candidate tiles: the default, then whole numbers of the kernel's sub-tile
+  const int sub = lps::sub_states(ctx, prec);
+  const int tiles[] = {0, sub, 2 * sub, 3 * sub, 4 * sub, 6 * sub, 8 * sub, 12 * sub};
+  constexpr int n_tiles_c = sizeof(tiles) / sizeof(tiles[0]);
   const int pi = prec == LPS_MIXED ? 1 : 0;
   const lps::LaunchShape saved = ctx->fwd_shape[pi];
   const int saved_timing = ctx->timing;
@@ -372,7 +375,7 @@ lps_status lps_autotune(lps_ctx* ctx, const lps_states* st, lps_precision prec, 
   lps::LaunchShape best_sh = saved;
   bool ok = true;
   for (int bi = 0; bi < 2 && ok; ++bi) {
-    for (int ti = 0; ti < 6 && ok; ++ti) {
+    for (int ti = 0; ti < n_tiles_c && ok; ++ti) {
       if (tiles[ti] > n) continue;
       ctx->fwd_shape[pi] = {bpl[pi][bi], tiles[ti]};
       ok = lps::launch_forward(ctx, st, prec, logL, nullptr, s) == hipSuccess;   // warm-up

@@ -654,12 +654,22 @@ hipError_t dispatch_wide(lps_ctx* ctx, int n_chunks, int chunk_bins, hipStream_t
 
 }  // namespace
 
-// States per tile: enough work items to fill the chip, at most 256 states.
-int auto_tile(int n_states, int n_chunks) {
-  const long target_items = 8192;   // ~32 waves per CU
-  long tile = ((long)n_states * n_chunks) / target_items;
-  if (tile < 1) tile = 1;
-  if (tile > 256) tile = 256;
+// States whose pieces one wave locates at once (the kernel's sub-tile): 64/G
+// pairs per wave, at most 32 (mixed) or 16 (FP64) states.
+int sub_states(const lps_ctx* ctx, lps_precision prec) {
+  const int per_wave = kWave / ctx->lay.n_grp;
+  const int cap = prec == LPS_MIXED ? 32 : 16;
+  return per_wave < cap ? per_wave : cap;
+}
+
+// States per tile: four sub-tiles (a tile that is not a whole number of
+// sub-tiles locates pieces for a partial one), fewer when that leaves too few
+// work items to fill the chip (~32 waves per CU).
+int auto_tile(int n_states, int n_chunks, int sub) {
+  const long target_items = 8192;
+  long tile = 4L * sub;
+  const long fill = ((long)n_states * n_chunks) / target_items;
+  if (fill < tile) tile = fill >= sub ? (fill / sub) * sub : (fill < 1 ? 1 : fill);
   if (tile > n_states) tile = n_states;
   return (int)tile;
 }
@@ -670,7 +680,7 @@ LaunchShape forward_shape(const lps_ctx* ctx, lps_precision prec, int n_states) 
   if (sh.bins_per_lane == 0) sh.bins_per_lane = prec == LPS_MIXED ? kB32 : kB64;
   const int chunk = kWave * sh.bins_per_lane;
   const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
-  if (sh.tile == 0) sh.tile = auto_tile(n_states, n_chunks);
+  if (sh.tile == 0) sh.tile = auto_tile(n_states, n_chunks, sub_states(ctx, prec));
   if (sh.tile > n_states) sh.tile = n_states;
   return sh;
 }

@@ -174,6 +174,7 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
                        double* dparams, double* dkx, double* dky, uint32_t* status, hipStream_t s);
 size_t grad_workspace_bytes(const lps_ctx* ctx);
 LaunchShape forward_shape(const lps_ctx* ctx, lps_precision prec, int n_states);
+int sub_states(const lps_ctx* ctx, lps_precision prec);
 bool valid_bins_per_lane(lps_precision prec, int b);
 
 // Chunk geometry of the batched kernels.
