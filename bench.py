@@ -145,7 +145,9 @@ def parse():
     p.add_argument("--no-paper", action="store_true", help="skip the paper-layout forward leg")
     p.add_argument("--no-small", action="store_true", help="skip the small-configuration legs")
     p.add_argument("--launch", default="",
-                   help="fixed launch shapes instead of autotuning, e.g. mixed=8x128,fp64=4x64")
+                   help="fixed launch shapes, e.g. mixed=8x84,fp64=4x64 (default: the library's default shapes)")
+    p.add_argument("--autotune", action="store_true",
+                   help="time the headline at the autotuner's pick instead of the library's default shapes")
     return p.parse_args()
 
 
@@ -465,18 +467,25 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # --- autotune the launch shape of each precision on this batch --------------
+    # --- launch shape of each precision: the library's default for this batch
+    # (deterministic, and the shape the committed counter summaries describe),
+    # a fixed one, or the autotuner's pick -------------------------------------
     shapes = {}
     fixed = dict(kv.split("=") for kv in args.launch.split(",") if kv)
     for prec in ("mixed", "fp64"):
+        ms, how = None, "default"
         if prec in fixed:
             b, t = (int(v) for v in fixed[prec].split("x"))
             ctx.set_launch(prec, b, t)
-            shp, ms = ctx.get_launch(prec, n), None
+            how = "fixed"
+        elif args.autotune:
+            ms, _ = ctx.autotune(st, prec, reps=3)
+            how = "autotuned"
         else:
-            ms, shp = ctx.autotune(st, prec, reps=3)
-        shapes[prec] = {"bins_per_lane": shp[0], "states_per_tile": shp[1], "autotune_ms": ms}
-        log(f"launch {prec}: bins/lane {shp[0]}, states/tile {shp[1]} ({'fixed' if ms is None else f'{ms:.3f} ms'})")
+            ctx.set_launch(prec, 0, 0)
+        shp = ctx.get_launch(prec, n)
+        shapes[prec] = {"bins_per_lane": shp[0], "states_per_tile": shp[1], "chosen": how, "autotune_ms": ms}
+        log(f"launch {prec}: bins/lane {shp[0]}, states/tile {shp[1]} ({how}{'' if ms is None else f', {ms:.3f} ms'})")
 
     # --- headline: mixed batched, graph-replayed -------------------------------
     log("mixed batched ...")

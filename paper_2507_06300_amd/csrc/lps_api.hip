@@ -190,6 +190,10 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   lps_ctx* c = new lps_ctx;
   memset(c, 0, sizeof(*c));
   c->device = device;
+  {
+    hipDeviceProp_t prop;
+    c->n_cu = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.multiProcessorCount : 0;
+  }
   c->n_bins = K;
   c->k_pad64 = ((K + lps::kChunk64 - 1) / lps::kChunk64) * lps::kChunk64;
   c->k_pad32 = ((K + lps::kChunk32 - 1) / lps::kChunk32) * lps::kChunk32;

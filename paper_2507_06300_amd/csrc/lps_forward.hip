@@ -32,11 +32,6 @@
 namespace lps {
 namespace {
 
-// A piece whose cubic term changes its exponent by at most this much (log2
-// units, about 1e-8 relative in 2^Q) anywhere in a chunk is evaluated as a
-// quadratic there.
-constexpr double kQuadTol = 1.0 / (1 << 26);
-
 // 2^q and log2(v) over the double-precision range with single-precision
 // accuracy: the integer part of the exponent is applied exactly (ldexp /
 // frexp) and only the fraction goes through the hardware transcendental.
@@ -184,14 +179,18 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
   // walks one contiguous range of that order.  A chunk's table rows then
   // reach an XCD's L2 once per tile group instead of once per tile, while the
   // group's state records (pieces, breakpoints) stay resident in that L2.
-  const int item = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+  // A wave takes items first, first + stride, ... (one item when the grid has
+  // a wave per item; a persistent grid of a few workgroups per CU strides).
+  const int n_items = n_chunks * n_tiles;
+  const int stride = gridDim.x * kWavesPerBlock;
+  for (int item = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wv; item < n_items; item += stride) {
   const int tg = item / (n_chunks * kTileGroup);
   const int rem = item - tg * (n_chunks * kTileGroup);
   const int tl = min(kTileGroup, n_tiles - tg * kTileGroup);   // tiles in this group
-  if (tl <= 0) return;
+  if (tl <= 0) continue;
   const int chunk = rem / tl;
   const int t = tg * kTileGroup + (rem - chunk * tl);
-  if (chunk >= n_chunks) return;
+  if (chunk >= n_chunks) continue;
   const int s_begin = t * tile;
   const int s_end = min(s_begin + tile, n_states);
   const int kbase = chunk * CH;
@@ -578,6 +577,7 @@ __global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int
     }
     wave_lds_sync();
   }
+  }   // items
 }
 
 // logL = C0 - sum over chunks (fixed order), -inf for invalid states.
@@ -605,7 +605,10 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
                     hipStream_t s) {
   const Layout& L = ctx->lay;
   const int items = n_chunks * n_tiles;
-  dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
+  int blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (kForwardPersistent && ctx->n_cu > 0 && blocks > ctx->n_cu * kPersistBlocksPerCu)
+    blocks = ctx->n_cu * kPersistBlocksPerCu;
+  dim3 grid(blocks), block(kWave * kWavesPerBlock);
   const int k_pad = sizeof(R) == 4 ? ctx->k_pad32 : ctx->k_pad64;
   constexpr int M = kMergeBins < B ? kMergeBins : B;
   const R nl_uni = (R)(ctx->nk_uniform * kLn2);
