@@ -222,8 +222,9 @@ lps_status lps_loglike_plain_fp64_noalloc(const lps_dataset_desc* desc /*[host]*
  * Launch shape of the batched forward kernel for one precision: bins per lane
  * (the wave's chunk is 64 times that; mixed: 4 or 8, FP64: 2 or 4) and states
  * per work item (1..4096).  0 selects the built-in default (mixed 8, FP64 4;
- * four of the kernel's sub-tiles of min(64 / groups, 32 mixed or 16 FP64)
- * states, fewer if that launches under about 8192 wave work items).
+ * six (mixed) or four (FP64) of the kernel's sub-tiles of min(64 / groups,
+ * 32 mixed or 16 FP64) states, fewer if that launches under about 8192 wave
+ * work items).
  */
 lps_status lps_set_launch(lps_ctx* ctx, lps_precision prec, int32_t bins_per_lane, int32_t states_per_tile);
 

@@ -134,8 +134,19 @@ __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int 
   }
 }
 
+// Waves per SIMD the register allocation must allow: four for the
+// single-precision split layout with merged A/E rows, no foreground and eight
+// bins per lane (the one-year workload's kernel: 128 registers and 40 bytes
+// spilled outside the bin loop, 5-7 % faster than three waves at 141
+// registers); the other instantiations would spill inside their bin loops at
+// four (the paper layout ran 6x slower) and keep the compiler's choice.
+template <typename R, int MODE, int NCH, bool FG, int B>
+struct FwdWaves {
+  static constexpr int v = (sizeof(R) == 4 && MODE == kSplit && NCH == 2 && !FG && B == 8) ? 4 : 1;
+};
+
 template <typename R, int MODE, int NCH, bool FG, int B, int M, bool UNI>
-__global__ __launch_bounds__(256) void k_forward(int n_states, int n_chunks, int n_tiles, int tile, int K,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R, MODE, NCH, FG, B>::v))) void k_forward(int n_states, int n_chunks, int n_tiles, int tile, int K,
                                                  int k_pad, int ref_chunk, R nl_uni, const R* __restrict__ tab,
                                                  const double* __restrict__ x64, const double* __restrict__ bx,
                                                  const R* __restrict__ coef, const double* __restrict__ coef64,
@@ -665,12 +676,13 @@ int sub_states(const lps_ctx* ctx, lps_precision prec) {
   return per_wave < cap ? per_wave : cap;
 }
 
-// States per tile: four sub-tiles (a tile that is not a whole number of
-// sub-tiles locates pieces for a partial one), fewer when that leaves too few
-// work items to fill the chip (~32 waves per CU).
-int auto_tile(int n_states, int n_chunks, int sub) {
+// States per tile: a whole number of sub-tiles (a tile that is not locates
+// pieces for a partial one), six in single precision and four in FP64 (the
+// fastest on the one-year workload), fewer when that leaves too few work items
+// to fill the chip (~32 waves per CU).
+int auto_tile(int n_states, int n_chunks, int sub, int subtiles) {
   const long target_items = 8192;
-  long tile = 4L * sub;
+  long tile = (long)subtiles * sub;
   const long fill = ((long)n_states * n_chunks) / target_items;
   if (fill < tile) tile = fill >= sub ? (fill / sub) * sub : (fill < 1 ? 1 : fill);
   if (tile > n_states) tile = n_states;
@@ -683,7 +695,7 @@ LaunchShape forward_shape(const lps_ctx* ctx, lps_precision prec, int n_states) 
   if (sh.bins_per_lane == 0) sh.bins_per_lane = prec == LPS_MIXED ? kB32 : kB64;
   const int chunk = kWave * sh.bins_per_lane;
   const int n_chunks = (ctx->n_bins + chunk - 1) / chunk;
-  if (sh.tile == 0) sh.tile = auto_tile(n_states, n_chunks, sub_states(ctx, prec));
+  if (sh.tile == 0) sh.tile = auto_tile(n_states, n_chunks, sub_states(ctx, prec), prec == LPS_MIXED ? 6 : 4);
   if (sh.tile > n_states) sh.tile = n_states;
   return sh;
 }

@@ -238,8 +238,17 @@ __device__ __noinline__ WideOut<G, B> redo_lane_wide(WideLane<G, NT, NCH, B> in)
   return o;
 }
 
+// Waves per SIMD the register allocation must allow: four for the
+// single-precision kernels with merged A/E rows (128 registers and about
+// 100 bytes more spilled than at three waves, outside the bin loop; 4 % faster
+// on the sampler workload), the compiler's choice otherwise.
+template <typename R, int NCH>
+struct GradWaves {
+  static constexpr int v = (sizeof(R) == 4 && NCH == 2) ? 4 : 1;
+};
+
 template <typename R, int MODE, int NCH, bool FG, int B>
-__global__ __launch_bounds__(256) void k_grad(int n_states, int n_chunks, int n_tiles, int tile, int K, int k_pad,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R, NCH>::v))) void k_grad(int n_states, int n_chunks, int n_tiles, int tile, int K, int k_pad,
                                               int ref_chunk, const R* __restrict__ tab,
                                               const double* __restrict__ x64, const double* __restrict__ bx,
                                               const R* __restrict__ coef, const double* __restrict__ coef64,

@@ -21,8 +21,8 @@ def test_more_than_one_gpu_is_refused():
 def test_profiles_match_the_kernel_sources():
     w = "year_912085bins_4096states"
     # the launch shape the library picks for this batch by default (8 bins per
-    # lane, four 21-state sub-tiles per work item), which the autotuner keeps
-    assert bench.profiled_traffic(w, (8, 84)) > 0
+    # lane, six 21-state sub-tiles per work item)
+    assert bench.profiled_traffic(w, (8, 126)) > 0
     assert bench.profiled_forward_field(w, "valu_lane_instr_per_state_bin_fp64") > 0
     assert bench.profiled_cov_valu() > 0
     assert bench.profiled_cov_grad_valu() > 0
