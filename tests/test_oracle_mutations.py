@@ -137,6 +137,17 @@ def test_mutation_alpha_pivot(monkeypatch):
     assert _fails(pins.test_sgwb_template_scalings)
 
 
+@pytest.mark.parametrize("factor", [4.0 * math.pi ** 2, 3.0, 0.5])
+def test_mutation_sgwb_constant(monkeypatch, factor):
+    orig = O.sgwb_tdi
+
+    def wrong(f, R, u, alpha, f_knee):
+        return orig(f, R, u, alpha, f_knee) * factor       # 4 pi^2 or 3 dropped, a one-sided/two-sided slip
+
+    monkeypatch.setattr(O, "sgwb_tdi", wrong)
+    assert _fails(pins.test_cosmic_string_background_has_the_papers_snr)
+
+
 def test_mutation_route_transposed(monkeypatch):
     orig = O.perturbed_terms
 

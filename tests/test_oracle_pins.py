@@ -418,3 +418,18 @@ def test_gradient_identities(seed_offset):
     tilt = math.fsum(kx * dys[2])
     expect = dp[3] + math.log10(ds.f_knee) * dp[2]
     assert abs(tilt - expect) <= 1e-8 * (abs(expect) + 1)
+
+
+def test_cosmic_string_background_has_the_papers_snr():
+    """Sec. "Data generation": the cosmic-string background of Eq. (cs) with
+    G mu = 1e-13 (flat spectrum), one year of data in the band [1e-4, 2.9e-2] Hz
+    at the noise amplitudes of Sec. "Parametrized noise model" (7.9 pm, 2.4 fm),
+    has SNR 262 by Eq. (snr).  The response is an
+    input here (a stand-in whose normalisation was fitted to that number once and
+    is committed in synth/workloads.py); with it fixed, the printed SNR pins the
+    absolute scale of S_h = R h^2 Omega 3 (H0/h)^2 / (4 pi^2 f^3) of Eq. (Sh)
+    against the noise of Eq. (noise_tdi), which is the only combination of the
+    two that the likelihood sees."""
+    ds = W.make_dataset("year_912085bins_4096states")
+    params = np.array([7.9e-12, 2.4e-15, math.log10(0.55e-11), 0.0])
+    assert abs(O.snr(ds, params) - 262.0) < 0.05
