@@ -200,9 +200,9 @@ __host__ __device__ inline double block_origin(const double* x, int kb, int K) {
 constexpr int kPlainBlock = 256;
 
 // A piece whose cubic term changes its exponent by at most this much (log2
-// units, about 1e-8 relative in 2^Q) anywhere in a chunk is evaluated as a
-// quadratic there (single-precision kernels).
-constexpr double kQuadTol = 1.0 / (1 << 26);
+// units, 4e-8 relative in 2^Q: under one unit in the last place of a single-
+// precision result) anywhere in a chunk is evaluated as a quadratic there.
+constexpr double kQuadTol = 1.0 / (1 << 24);
 
 // ---------------------------------------------------------------------------
 // Wave-level helpers
