@@ -103,7 +103,7 @@ __global__ void k_cov_table(int K, int k_pad, const double* __restrict__ f, cons
     row[kRfg + c] = Rfg ? Rfg[c * (size_t)K + kk] * is : 0.0;
   }
   for (int i = 0; i < 6; ++i) row[kRP + i] = k < K ? P[i * (size_t)K + kk] * is : 0.0;
-  for (int r = 0; r < kCovRows; ++r) tab[r * (size_t)k_pad + k] = row[r];
+  for (int r = 0; r < kCovRows; ++r) tab[tab_index(r, k)] = row[r];
   if (k < K) sig[k] = sigma;
 }
 
@@ -174,13 +174,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   const int ns = t < A.n_tiles ? min(A.tile, A.n_states - s0) : 0;
   const int c_begin = g * A.chunks_per_group;
   const int c_end = min(A.n_chunks, c_begin + A.chunks_per_group);
-  const size_t kp = (size_t)A.k_pad;
   lval[w][kSlotOne][lane] = 1.0;
   lval[w][kSlotZero][lane] = 0.0;
   const LdsVal val{&lval[w][0][lane]};
 
   // cursors at the first bin of the group (lane = piece)
-  const double xg = A.tab[kRx * kp + (size_t)c_begin * kCovChunk];
+  const double xg = A.tab[tab_index(kRx, (size_t)c_begin * kCovChunk)];
   for (int i = 0; i < ns; ++i) {
     const int s = s0 + i;
     if (A.status[s] != 0u) continue;
@@ -208,8 +207,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   int* const lcur_w = &lcur[w][0][0][0];
   for (int ch = c_begin; ch < c_end; ++ch) {
     const int kb = ch * kCovChunk;
-    const double* tb = A.tab + kb + lane;   // row r, bin b of the chunk: tb[r * kp + b * kWave]
-    const double xl = A.tab[kRx * kp + kb + kCovChunk - 1];
+    const double* tb = A.tab + tab_index(0, kb) + lane;   // row r, bin b of the chunk: tb[b * kCovBlock + r * kWave]
+    const double xl = A.tab[tab_index(kRx, kb + kCovChunk - 1)];
     for (int i = 0; i < ns; ++i) {
       const int s = s0 + i;
       if (A.status[s] != 0u) continue;
@@ -236,7 +235,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       bool bad = false;
 #pragma unroll 1
       for (int b = 0; b < kCovB; ++b) {
-        const double x = tb[kRx * kp + b * kWave];
+        const double x = tb[(size_t)b * kCovBlock + kRx * kWave];
         const double lin = sc.u + sc.alpha * (x - A.x_knee);
 #pragma unroll 1
         for (int j = 0; j < A.n_spl; ++j) {
@@ -258,7 +257,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
           }
           lval[w][j][lane] = slot_value(pv, j, A.rt, lin);
         }
-        const TabRow row{tb + b * kWave, kp};
+        const TabRow row{tb + (size_t)b * kCovBlock};
         CovPoint p;
         cov_point(val, A.rt, sc, A.x_knee, row, p);
         v += cov_term(p, row, bad);
@@ -312,7 +311,7 @@ __global__ void k_cov_build(int n_states, int k0, int n_out, int k_pad, const do
     for (int e = 0; e < 6; ++e) out[(size_t)e * n_out] = NAN;
     return;
   }
-  const TabRow row{tab + k, (size_t)k_pad};
+  const TabRow row{tab + tab_index(0, k)};
   const double x = row(kRx);
   const StateScal sc = state_scalars(params, n_states, s, has_fg);
   const double lin = sc.u + sc.alpha * (x - x_knee);

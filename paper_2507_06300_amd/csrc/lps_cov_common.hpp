@@ -50,8 +50,10 @@ constexpr int kCovChunk = kWave * kCovB;    // 128 bins
 constexpr int kCovMaxTile = 8;              // states per wave
 constexpr int kCovGroups = 64;              // chunk groups per dataset (fixed by K alone)
 
-// Rows of the per-bin table [kCovRows][k_pad]; every PSD-valued row is
-// divided by sigma_k.
+// Rows of the per-bin table; every PSD-valued row is divided by sigma_k.  The
+// table is stored in blocks of 64 consecutive bins, each holding its rows one
+// after the other ([k_pad / 64][kCovRows][64], tab_index), so that a lane's
+// entries of one bin lie at fixed offsets from a single address.
 enum : int {
   kRx = 0,       // log10 f
   kRnu = 1,      // N_k (0 for padding)
@@ -89,7 +91,7 @@ struct lps_cov_ctx {
   int32_t n_spl, n_params, k_max, max_states, has_fg;
   lps::covk::CovRoute rt;
   double x_knee, x_first, x_last;
-  double* tab;          // [kCovRows][k_pad]
+  double* tab;          // [k_pad / 64][kCovRows][64] (tab_index)
   double* bx;           // [max_states][kCovMaxSpl][kMaxKnots] piece start abscissae
   double* coef;         // [max_states][kCovMaxSpl][kMaxKnots][4]
   int32_t* npc;         // [max_states][kCovMaxSpl] pieces (0: disabled or invalid state)
@@ -119,11 +121,14 @@ __device__ inline StateScal state_scalars(const double* __restrict__ params, int
   return r;
 }
 
-__device__ inline double exp10_d(double y) { return exp2_d(y * kLog2_10); }
+// kSgpr: polynomial coefficients in scalar registers (see fma3).
+template <bool kSgpr = false>
+__device__ inline double exp10_d(double y) { return exp2_d<kSgpr>(y * kLog2_10); }
 
 // tanh q = sign(q) (1 - e) / (1 + e), e = exp(-2|q|) in (0, 1]
+template <bool kSgpr = false>
 __device__ inline double tanh_d(double q) {
-  const double e = exp2_d(-2.0 * kLog2e * fabs(q));
+  const double e = exp2_d<kSgpr>(-2.0 * kLog2e * fabs(q));
   const double den = 1.0 + e, num = 1.0 - e;
   const double r = rcp_d(den);
   const double t = num * r;
@@ -140,17 +145,19 @@ struct CovPoint {
 // lin = u + alpha (x - log10 f_knee) is added to the exponent of the slot that
 // carries the background in every channel (rt.sg_slot), which then holds the
 // whole background factor 10^(u + alpha (x - x_knee) + P).
+template <bool kSgpr = false>
 __device__ inline double slot_value(double pv, int j, const CovRoute& rt, double lin) {
-  if (j == rt.sg_slot) return exp10_d(pv + lin);
-  if ((rt.diag_mask >> j) & 1u) return exp10_d(pv);
-  if ((rt.corr_mask >> j) & 1u) return tanh_d(pv);
+  if (j == rt.sg_slot) return exp10_d<kSgpr>(pv + lin);
+  if ((rt.diag_mask >> j) & 1u) return exp10_d<kSgpr>(pv);
+  if ((rt.corr_mask >> j) & 1u) return tanh_d<kSgpr>(pv);
   return pv;
 }
 
 // The power-law factor 10^(u + alpha (x - x_knee)) of the background, or 1
 // where the slot rt.sg_slot already carries it.
+template <bool kSgpr = false>
 __device__ inline double background_factor(const CovRoute& rt, const StateScal& sc, double x, double x_knee) {
-  return rt.sg_slot >= 0 ? 1.0 : exp10_d(sc.u + sc.alpha * (x - x_knee));
+  return rt.sg_slot >= 0 ? 1.0 : exp10_d<kSgpr>(sc.u + sc.alpha * (x - x_knee));
 }
 
 // The model at one bin from the slot values V (read through `val(slot)`), the
@@ -206,12 +213,12 @@ __device__ inline CovAdj cov_adj(const CovPoint& p) {
 
 // N_k (tr(C^-1 P) + ln det C) at one bin in scaled units from the cofactors;
 // `bad` is set where C is not positive definite or the term is not finite.
-template <typename Row>
+template <bool kSgpr = false, typename Row>
 __device__ inline double cov_term_adj(const CovAdj& c, const CovPoint& p, const Row& row, bool& bad) {
   const double num = c.a00 * row(kRP + 0) + c.a11 * row(kRP + 1) + c.a22 * row(kRP + 2) +
                      2.0 * (c.a01 * row(kRP + 3) + c.a02 * row(kRP + 4) + c.a12 * row(kRP + 5));
   const double tr = num / c.det;
-  const double ld = log_d(c.det);
+  const double ld = log_d<kSgpr>(c.det);
   const bool ok = p.d[0] > 0.0 && c.a22 > 0.0 && c.det > 0.0 && isfinite(tr) && isfinite(ld);
   bad = bad || !ok;
   return row(kRnu) * (tr + ld);
@@ -241,10 +248,17 @@ struct LdsVal {
   __device__ double operator()(int j) const { return p[j * kWave]; }
 };
 
+constexpr int kCovBlock = kCovRows * kWave;   // doubles per 64-bin block of the table
+
+// Position of row r, bin k in the blocked table.
+__host__ __device__ inline size_t tab_index(int r, size_t k) {
+  return (k / kWave) * kCovBlock + (size_t)r * kWave + (k % kWave);
+}
+
+// The entries of one bin: p = &tab[tab_index(0, k)], rows kWave apart.
 struct TabRow {
   const double* __restrict__ p;
-  size_t stride;
-  __device__ double operator()(int r) const { return p[r * stride]; }
+  __device__ double operator()(int r) const { return p[r * kWave]; }
 };
 
 // The piece of spline (s, j) that holds a bin and the start of the next one.

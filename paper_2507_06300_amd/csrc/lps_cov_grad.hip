@@ -30,50 +30,56 @@ using namespace covk;
 // dq = dr (1 - r^2) for r = tanh q, and d(10^P)/dP = ln 10 10^P for the level
 // slots.  The slot derivatives dlogL/dP_j(x) are summed per spline piece as
 // moments M_m = sum dP t^m (t from the piece start), and the Akima backward
-// turns them into knot derivatives.  A lane keeps the moments of the piece
-// under the cursor in registers; a chunk that crosses a knot adds the bins
-// beyond it piece by piece (wave sums) and the finished piece's moments go to
-// the state's moment table in global memory, where lane q alone reads and
+// turns them into knot derivatives.
+//
+// The wave walks the band in passes of 64 bins, one bin per lane, in three
+// phases: the spline values (one spline at a time), the bin's model and its
+// adjoint, then the moments.  The adjoint adds each of its derivative terms
+// (OMS, TM and background per channel, three correlations) into the slot it is
+// routed to with an LDS atomic add (no read-modify-write in the wave), and
+// the moment phase reads one sum per spline.  A lane keeps the moments of the
+// piece under the cursor in registers; a pass that crosses a knot adds the
+// bins beyond it piece by piece (wave sums), and a finished piece's moments go
+// to the state's moment table in global memory, where lane q alone reads and
 // writes the entries of piece q (so no fence is needed between the lanes).
+// The cursor state is uniform and held across lanes of two registers, picked
+// by lane index: lane 3j + f of cv holds field f of spline j (the piece under
+// the cursor, the last piece this pass reaches, the number of pieces) and
+// lane 6j + f of rec field f of that piece (start, four coefficients, start
+// of the next piece), so no cursor read waits on memory.
 // ---------------------------------------------------------------------------
-// Per wave; the kCovB bins of a lane go through each phase together (their
-// arithmetic is independent, which gives the scheduler two chains to
-// interleave).  Slots kSlotOne and kSlotZero of gp collect the derivatives
-// of terms that no spline perturbs; they are never read.  val, gp, t and pc
-// are lane-private columns; rec is written by lane 0 and read by every lane.
-struct CovGradLds {
-  double val[kCovB][kSlots][kWave];      // slot values of the lane's bins
-  double gp[kCovB][kSlots][kWave];       // dlogL / d(slot argument)
-  double t[kCovB][kCovMaxSpl][kWave];    // x - start of the bin's piece
-  int pc[kCovB][kCovMaxSpl][kWave];      // the bin's piece
-  PieceRec rec[kCovMaxSpl];              // the piece under each spline's cursor
-};
-static_assert(sizeof(BackLds) <= sizeof(double) * kCovB * kSlots * kWave, "backward LDS aliases val");
 
-struct RegRow {
-  double v[kCovRows];
-  __device__ double operator()(int r) const { return v[r]; }
+// Per wave; lane-private columns.  The Akima backward at the end reuses them.
+struct CovGradLds {
+  double val[kSlots][kWave];   // slot values of the lane's bin
+  double gp[kSlots][kWave];    // dlogL / d(slot argument) of the lane's bin
 };
+static_assert(sizeof(BackLds) <= sizeof(CovGradLds), "backward LDS aliases val and gp");
 
 __device__ inline void mo_add(double* __restrict__ m, const double (&v)[4]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) m[i] += v[i];
 }
 
-__global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict__ mo_ws,
-                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, int64_t n_knots,
-                                                  const double* __restrict__ kx, const double* __restrict__ ky,
-                                                  int n_params, const double* __restrict__ c0,
-                                                  double* __restrict__ logL, double* __restrict__ dparams,
-                                                  double* __restrict__ dkx, double* __restrict__ dky,
-                                                  uint32_t* __restrict__ status_out) {
+__device__ inline void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// NS >= n_spl: the splines whose piece moments a lane keeps in registers.
+// Two waves per SIMD; the polynomial coefficients of exp2 and log sit in scalar
+// registers, since the moment accumulators leave few vector registers.
+template <int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_cov_grad(
+    CovArgs A, double* __restrict__ mo_ws, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt,
+    int64_t n_knots, const double* __restrict__ kx, const double* __restrict__ ky, int n_params,
+    const double* __restrict__ c0, double* __restrict__ logL, double* __restrict__ dparams, double* __restrict__ dkx,
+    double* __restrict__ dky, uint32_t* __restrict__ status_out) {
   __shared__ CovGradLds lds[4];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = (int)(threadIdx.x / kWave);
   const int s = uniform(blockIdx.x * 4 + w);
   if (s >= A.n_states) return;
   CovGradLds& L = lds[w];
-  const size_t kp = (size_t)A.k_pad;
   const int n_spl = A.n_spl;
   uint32_t st = A.status[s];
   auto zero_outputs = [&]() {
@@ -81,7 +87,6 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
     for (int j = 0; j < n_spl; ++j) {
       int a, cn;
       knot_range(off, kcnt, s * n_spl + j, n_knots, a, cn);
-      if (a < 0) continue;
       for (int i = lane; i < cn; i += kWave) {
         dkx[a + i] = 0.0;
         dky[a + i] = 0.0;
@@ -100,245 +105,229 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
   for (int j = 0; j < n_spl; ++j)
 #pragma unroll
     for (int m = 0; m < 4; ++m) mo[((size_t)j * kMaxKnots + lane) * 4 + m] = 0.0;
-  // cursors at the first bin.  The cursor state is uniform and lives in
-  // scalar registers (the spline loops are unrolled): cur = piece under the
-  // cursor (-1: disabled spline), hi = last piece that this chunk reaches,
-  // npc = pieces, xn = start of the piece after the cursor.
-  const double x_first = A.tab[kRx * kp];
-  int cur[kCovMaxSpl], hi[kCovMaxSpl], npc[kCovMaxSpl];
-  double xn[kCovMaxSpl];
-#pragma unroll
-  for (int j = 0; j < kCovMaxSpl; ++j) {
-    cur[j] = -1;
-    hi[j] = -1;
-    npc[j] = 0;
-    xn[j] = INFINITY;
-    if (j >= n_spl) continue;
+  // lanes 6j .. 6j + 5 of rec take piece q of spline j
+  double rec = 0.0;
+  auto load_rec = [&](int j, int q, int np) {
+    const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
+    const int f = lane - 6 * j;
+    if (f == 0) rec = A.bx[row + q];
+    else if (f >= 1 && f <= 4) rec = A.coef[(row + q) * 4 + (f - 1)];
+    else if (f == 5) rec = q + 1 < np ? A.bx[row + q + 1] : INFINITY;
+  };
+  // cursors at the first bin
+  const double x_first = A.tab[tab_index(kRx, 0)];
+  int cv = 0;
+#pragma unroll 1
+  for (int j = 0; j < n_spl; ++j) {
     const int np = uniform(A.npc[(size_t)s * kCovMaxSpl + j]);
-    npc[j] = np;
+    int cur = -1;
     if (np > 0) {
       const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
       const double bl = lane < np ? A.bx[row + lane] : INFINITY;
-      cur[j] = uniform(max(__popcll(__ballot(bl <= x_first)) - 1, 0));
-      hi[j] = cur[j];
-      const PieceRec pr = load_piece(A, row, cur[j], np);
-      xn[j] = pr.xn;
-      if (lane == 0) L.rec[j] = pr;
+      cur = uniform(max(__popcll(__ballot(bl <= x_first)) - 1, 0));
+      load_rec(j, cur, np);
     }
+    cv = lane == 3 * j || lane == 3 * j + 1 ? cur : (lane == 3 * j + 2 ? np : cv);
   }
+  L.val[kSlotOne][lane] = 1.0;
+  L.val[kSlotZero][lane] = 0.0;
 #pragma unroll
-  for (int bb = 0; bb < kCovB; ++bb) {
-    L.val[bb][kSlotOne][lane] = 1.0;
-    L.val[bb][kSlotZero][lane] = 0.0;
-  }
-  wave_lds_sync();
+  for (int j = 0; j < kSlots; ++j) L.gp[j][lane] = 0.0;
   const StateScal sc = state_scalars(A.params, A.n_states, s, A.has_fg);
-  double acc[kCovMaxSpl][4];
+  double acc[NS][4];
 #pragma unroll
-  for (int j = 0; j < kCovMaxSpl; ++j)
+  for (int j = 0; j < NS; ++j)
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc[j][m] = 0.0;
   double lsum = 0.0, g_wo = 0.0, g_wt = 0.0, g_lin = 0.0, g_linx = 0.0, g_fg = 0.0;
   bool bad = false;
-  for (int ch = 0; ch < A.n_chunks; ++ch) {
-    const int kb = ch * kCovChunk;
-    const double* tb = A.tab + kb + lane;
-    const double xl = A.tab[kRx * kp + kb + kCovChunk - 1];
-    // pieces that start inside this chunk
-#pragma unroll
-    for (int j = 0; j < kCovMaxSpl; ++j) {
-      if (j >= n_spl) break;
-      if (cur[j] < 0 || !(xl >= xn[j])) continue;
+  const int n_pass = A.n_chunks * (kCovChunk / kWave);
+  const double* const xrow = A.tab + kRx * kWave + lane;
+  double x_next = xrow[0];   // the abscissae one pass ahead
+  for (int ps = 0; ps < n_pass; ++ps) {
+    const int kb = ps * kWave;
+    const double x = x_next;
+    if (ps + 1 < n_pass) x_next = xrow[(size_t)(ps + 1) * kCovBlock];
+    const double xl = readlane_r(x, kWave - 1);
+    // pieces that start inside this pass
+#pragma unroll 1
+    for (int j = 0; j < n_spl; ++j) {
+      const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+      if (cur < 0 || !(xl >= readlane_r(rec, 6 * j + 5))) continue;
+      const int np = __builtin_amdgcn_readlane(cv, 3 * j + 2);
       const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-      int h = cur[j] + 1;
-      while (h + 1 < npc[j] && A.bx[row + h + 1] <= xl) ++h;
-      hi[j] = h;
+      int h = cur + 1;
+      while (h + 1 < np && A.bx[row + h + 1] <= xl) ++h;
+      cv = lane == 3 * j + 1 ? h : cv;
     }
-    // the bins' table entries, loaded ahead of the LDS exchanges below (whose
-    // fences would otherwise hold every load back until the spline work is done)
-    RegRow row[kCovB];
-    double x[kCovB], lin[kCovB];
-#pragma unroll
-    for (int bb = 0; bb < kCovB; ++bb) {
-#pragma unroll
-      for (int r = 0; r < kCovRows; ++r) row[bb].v[r] = tb[bb * kWave + r * kp];
-      x[bb] = row[bb](kRx);
-      lin[bb] = sc.u + sc.alpha * (x[bb] - A.x_knee);
-    }
-    // forward: slot values, the bin's piece and abscissa offset per spline
-#pragma unroll
-    for (int j = 0; j < kCovMaxSpl; ++j) {
-      if (j >= n_spl) break;
-      const int cur_j = cur[j];
-      double pv[kCovB], tt[kCovB];
-      int pc[kCovB];
-      if (cur_j >= 0) {
-        PieceRec pr[kCovB];
-#pragma unroll
-        for (int bb = 0; bb < kCovB; ++bb) {
-          pr[bb] = L.rec[j];
-          pc[bb] = cur_j;
-        }
-        if (hi[j] != cur_j) {
-          const size_t rw = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
-          for (int q = cur_j + 1; q <= hi[j]; ++q) {
-            const PieceRec nq = load_piece(A, rw, q, npc[j]);
-#pragma unroll
-            for (int bb = 0; bb < kCovB; ++bb)
-              if (x[bb] >= nq.x0) {
-                pr[bb] = nq;
-                pc[bb] = q;
-              }
+    const TabRow rw{A.tab + (size_t)ps * kCovBlock + lane};
+    // spline values
+    const double lin = sc.u + sc.alpha * (x - A.x_knee);
+#pragma unroll 1
+    for (int j = 0; j < n_spl; ++j) {
+      const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+      double pv = 0.0;
+      if (cur >= 0) {
+        double x0 = readlane_r(rec, 6 * j), a0 = readlane_r(rec, 6 * j + 1), a1 = readlane_r(rec, 6 * j + 2);
+        double a2 = readlane_r(rec, 6 * j + 3), a3 = readlane_r(rec, 6 * j + 4);
+        const int hi = __builtin_amdgcn_readlane(cv, 3 * j + 1);
+        if (hi != cur) {
+          const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
+          const int np = __builtin_amdgcn_readlane(cv, 3 * j + 2);
+          for (int q = cur + 1; q <= hi; ++q) {
+            const PieceRec nq = load_piece(A, row, q, np);
+            if (x >= nq.x0) {
+              x0 = nq.x0;
+              a0 = nq.a0;
+              a1 = nq.a1;
+              a2 = nq.a2;
+              a3 = nq.a3;
+            }
           }
         }
-#pragma unroll
-        for (int bb = 0; bb < kCovB; ++bb) {
-          tt[bb] = x[bb] - pr[bb].x0;
-          pv[bb] = pr[bb].a0 + tt[bb] * (pr[bb].a1 + tt[bb] * (pr[bb].a2 + tt[bb] * pr[bb].a3));
-        }
-      } else {
-#pragma unroll
-        for (int bb = 0; bb < kCovB; ++bb) {
-          pv[bb] = 0.0;
-          tt[bb] = 0.0;
-          pc[bb] = cur_j;
-        }
+        const double tt = x - x0;
+        pv = a0 + tt * (a1 + tt * (a2 + tt * a3));
       }
-#pragma unroll
-      for (int bb = 0; bb < kCovB; ++bb) {
-        L.val[bb][j][lane] = slot_value(pv[bb], j, A.rt, lin[bb]);
-        L.t[bb][j][lane] = tt[bb];
-        L.pc[bb][j][lane] = pc[bb];
-        L.gp[bb][j][lane] = 0.0;
-      }
+      L.val[j][lane] = slot_value<true>(pv, j, A.rt, lin);
     }
-    wave_lds_sync();
-#pragma unroll
-    for (int bb = 0; bb < kCovB; ++bb) {
-      const LdsVal val{&L.val[bb][0][lane]};
-      const RegRow& rw = row[bb];
+    // the bin's model and adjoint
+    {
+      const LdsVal val{&L.val[0][lane]};
+      const double hf = background_factor<true>(A.rt, sc, x, A.x_knee);
       CovPoint p;
-      cov_point(val, A.rt, sc, A.x_knee, rw, p);
+      cov_point_h(val, A.rt, sc, hf, rw, p);
       const CovAdj cj = cov_adj(p);
-      lsum += cov_term_adj(cj, p, rw, bad);
-      // adjoint of the bin
+      lsum += cov_term_adj<true>(cj, p, rw, bad);
       const double nu = rw(kRnu);
-      const double n0 = p.sn[0], n1 = p.sn[1], n2 = p.sn[2];
-      const double c01 = p.r01 * cj.s01, c02 = p.r02 * cj.s02, c12 = p.r12 * cj.s12;
       const double id = rcp_d(cj.det);
-      const double ci[3][3] = {{cj.a00 * id, cj.a01 * id, cj.a02 * id},
-                               {cj.a01 * id, cj.a11 * id, cj.a12 * id},
-                               {cj.a02 * id, cj.a12 * id, cj.a22 * id}};
-      const double P[3][3] = {{rw(kRP + 0), rw(kRP + 3), rw(kRP + 4)},
-                              {rw(kRP + 3), rw(kRP + 1), rw(kRP + 5)},
-                              {rw(kRP + 4), rw(kRP + 5), rw(kRP + 2)}};
-      double X[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) X[a][c] = ci[a][0] * P[0][c] + ci[a][1] * P[1][c] + ci[a][2] * P[2][c];
-      auto Gm = [&](int a, int c) { return ci[a][c] - (X[a][0] * ci[0][c] + X[a][1] * ci[1][c] + X[a][2] * ci[2][c]); };
+      const double ci00 = cj.a00 * id, ci11 = cj.a11 * id, ci22 = cj.a22 * id;
+      const double ci01 = cj.a01 * id, ci02 = cj.a02 * id, ci12 = cj.a12 * id;
+      const double P00 = rw(kRP + 0), P11 = rw(kRP + 1), P22 = rw(kRP + 2);
+      const double P01 = rw(kRP + 3), P02 = rw(kRP + 4), P12 = rw(kRP + 5);
+      // X = C^-1 P (row a, column c), then G = C^-1 - X C^-1 (symmetric)
+      const double X00 = ci00 * P00 + ci01 * P01 + ci02 * P02;
+      const double X01 = ci00 * P01 + ci01 * P11 + ci02 * P12;
+      const double X02 = ci00 * P02 + ci01 * P12 + ci02 * P22;
+      const double X10 = ci01 * P00 + ci11 * P01 + ci12 * P02;
+      const double X11 = ci01 * P01 + ci11 * P11 + ci12 * P12;
+      const double X12 = ci01 * P02 + ci11 * P12 + ci12 * P22;
+      const double X20 = ci02 * P00 + ci12 * P01 + ci22 * P02;
+      const double X21 = ci02 * P01 + ci12 * P11 + ci22 * P12;
+      const double X22 = ci02 * P02 + ci12 * P12 + ci22 * P22;
+      const double G00 = ci00 - (X00 * ci00 + X01 * ci01 + X02 * ci02);
+      const double G11 = ci11 - (X10 * ci01 + X11 * ci11 + X12 * ci12);
+      const double G22 = ci22 - (X20 * ci02 + X21 * ci12 + X22 * ci22);
+      const double G01 = ci01 - (X00 * ci01 + X01 * ci11 + X02 * ci12);
+      const double G02 = ci02 - (X00 * ci02 + X01 * ci12 + X02 * ci22);
+      const double G12 = ci12 - (X10 * ci02 + X11 * ci12 + X12 * ci22);
       // dlogL / dC (pairs counted once)
-      const double gC00 = -nu * Gm(0, 0), gC11 = -nu * Gm(1, 1), gC22 = -nu * Gm(2, 2);
-      const double gC01 = -2.0 * nu * Gm(0, 1), gC02 = -2.0 * nu * Gm(0, 2), gC12 = -2.0 * nu * Gm(1, 2);
+      const double gC00 = -nu * G00, gC11 = -nu * G11, gC22 = -nu * G22;
+      const double gC01 = -2.0 * nu * G01, gC02 = -2.0 * nu * G02, gC12 = -2.0 * nu * G12;
+      const double c01 = p.r01 * cj.s01, c02 = p.r02 * cj.s02, c12 = p.r12 * cj.s12;
       const double gsh[3] = {gC00, gC11, gC22};
-      const double gsn[3] = {gC00 + (gC01 * c01 + gC02 * c02) * (0.5 * rcp_d(n0)),
-                             gC11 + (gC01 * c01 + gC12 * c12) * (0.5 * rcp_d(n1)),
-                             gC22 + (gC02 * c02 + gC12 * c12) * (0.5 * rcp_d(n2))};
+      const double gsn[3] = {gC00 + (gC01 * c01 + gC02 * c02) * (0.5 * rcp_d(p.sn[0])),
+                             gC11 + (gC01 * c01 + gC12 * c12) * (0.5 * rcp_d(p.sn[1])),
+                             gC22 + (gC02 * c02 + gC12 * c12) * (0.5 * rcp_d(p.sn[2]))};
       double gr01 = gC01 * cj.s01, gr02 = gC02 * cj.s02;
       const double gr12 = gC12 * cj.s12;
       const double pp = val(A.rt.gc[2]);
       const double S = sqrt_d((1.0 - p.r01 * p.r01) * (1.0 - p.r02 * p.r02));
-      const double gpp = gr12 * S;
       // S = 0 only where a correlation is exactly +-1; S is then 0 whatever the
       // other correlation, so its derivative terms drop out
       const double iS = S > 0.0 ? rcp_d(S) : 0.0;
       gr01 += gr12 * (p.r02 - pp * p.r01 * (1.0 - p.r02 * p.r02) * iS);
       gr02 += gr12 * (p.r01 - pp * p.r02 * (1.0 - p.r01 * p.r01) * iS);
-      const double gq[3] = {gr01 * (1.0 - p.r01 * p.r01), gr02 * (1.0 - p.r02 * p.r02), gpp * (1.0 - pp * pp)};
-      // slot derivatives (a slot may serve several terms: accumulate in LDS)
-      const double oms[3] = {rw(kRomsAE), rw(kRomsAE), rw(kRomsT)};
-      const double tm[3] = {rw(kRtmAE), rw(kRtmAE), rw(kRtmT)};
-      const double hf = background_factor(A.rt, sc, x[bb], A.x_knee);
+      lds_add(&L.gp[A.rt.gc[0]][lane], gr01 * (1.0 - p.r01 * p.r01));
+      lds_add(&L.gp[A.rt.gc[1]][lane], gr02 * (1.0 - p.r02 * p.r02));
+      lds_add(&L.gp[A.rt.gc[2]][lane], gr12 * S * (1.0 - pp * pp));
+      // level slots: the OMS, TM and background terms of each channel
       double gl = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double fo = val(A.rt.g[0][c]), ft = val(A.rt.g[1][c]), fh = val(A.rt.g[2][c]);
-        const double to = sc.w_oms * oms[c] * fo, tt2 = sc.w_tm * tm[c] * ft, th = rw(kRsg + c) * hf * fh;
-        g_wo += gsn[c] * oms[c] * fo;
-        g_wt += gsn[c] * tm[c] * ft;
-        g_fg += gsh[c] * rw(kRfg + c) * sc.efg;
+        const double oms = rw(c < 2 ? kRomsAE : kRomsT), tm = rw(c < 2 ? kRtmAE : kRtmT);
+        const double fo = oms * val(A.rt.g[0][c]), ft = tm * val(A.rt.g[1][c]);
+        const double th = rw(kRsg + c) * hf * val(A.rt.g[2][c]);
+        g_wo += gsn[c] * fo;
+        g_wt += gsn[c] * ft;
+        g_fg += gsh[c] * rw(kRfg + c);
         gl += gsh[c] * th;
-        L.gp[bb][A.rt.g[0][c]][lane] += kLn10 * gsn[c] * to;
-        L.gp[bb][A.rt.g[1][c]][lane] += kLn10 * gsn[c] * tt2;
-        L.gp[bb][A.rt.g[2][c]][lane] += kLn10 * gsh[c] * th;
+        lds_add(&L.gp[A.rt.g[0][c]][lane], kLn10 * gsn[c] * (sc.w_oms * fo));
+        lds_add(&L.gp[A.rt.g[1][c]][lane], kLn10 * gsn[c] * (sc.w_tm * ft));
+        lds_add(&L.gp[A.rt.g[2][c]][lane], kLn10 * gsh[c] * th);
       }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) L.gp[bb][A.rt.gc[i]][lane] += gq[i];
       g_lin += kLn10 * gl;
-      g_linx += kLn10 * gl * (x[bb] - A.x_knee);
+      g_linx += kLn10 * gl * (x - A.x_knee);
     }
-    wave_lds_sync();
-    // moments: the cursor piece in registers, later pieces of a crossing chunk by wave sums
+    // moments: the cursor piece in registers, later pieces of a crossing pass by wave sums
+    double gj[NS];
 #pragma unroll
-    for (int j = 0; j < kCovMaxSpl; ++j) {
+    for (int j = 0; j < NS; ++j) {
+      gj[j] = L.gp[j][lane];
+      L.gp[j][lane] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
       if (j >= n_spl) break;
-      if (cur[j] < 0) continue;
-      double v4[kCovB][4];
-      int pc[kCovB];
-#pragma unroll
-      for (int bb = 0; bb < kCovB; ++bb) {
-        const double g = L.gp[bb][j][lane], tt = L.t[bb][j][lane];
-        pc[bb] = L.pc[bb][j][lane];
-        const double u1 = g * tt, u2 = u1 * tt;
-        v4[bb][0] = g;
-        v4[bb][1] = u1;
-        v4[bb][2] = u2;
-        v4[bb][3] = u2 * tt;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[j][m] += pc[bb] == cur[j] ? v4[bb][m] : 0.0;
-      }
-      for (int q = cur[j] + 1; q <= hi[j]; ++q) {
-        double sq[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          double v = 0.0;
-#pragma unroll
-          for (int bb = 0; bb < kCovB; ++bb) v += pc[bb] == q ? v4[bb][m] : 0.0;
-          sq[m] = wave_sum(v);
+      const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+      if (cur < 0) continue;
+      const double g = gj[j];
+      const int hi = __builtin_amdgcn_readlane(cv, 3 * j + 1);
+      double tt = x - readlane_r(rec, 6 * j);
+      int pc = cur;
+      if (hi != cur) {
+        const size_t row = ((size_t)s * kCovMaxSpl + j) * kMaxKnots;
+        for (int q = cur + 1; q <= hi; ++q) {
+          const double xq = A.bx[row + q];
+          if (x >= xq) {
+            tt = x - xq;
+            pc = q;
+          }
         }
-        if (lane == q) mo_add(mo + ((size_t)j * kMaxKnots + q) * 4, sq);
+      }
+      const double u1 = g * tt, u2 = u1 * tt;
+      const double v4[4] = {g, u1, u2, u2 * tt};
+      if (hi == cur) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[j][m] += v4[m];
+      } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[j][m] += pc == cur ? v4[m] : 0.0;
+        for (int q = cur + 1; q <= hi; ++q) {
+          double sq[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) sq[m] = wave_sum(pc == q ? v4[m] : 0.0);
+          if (lane == q) mo_add(mo + ((size_t)j * kMaxKnots + q) * 4, sq);
+        }
       }
     }
-    wave_lds_sync();
     // finished pieces: flush the cursor piece and move the cursor
 #pragma unroll
-    for (int j = 0; j < kCovMaxSpl; ++j) {
+    for (int j = 0; j < NS; ++j) {
       if (j >= n_spl) break;
-      if (cur[j] < 0 || hi[j] == cur[j]) continue;
+      const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+      const int hi = __builtin_amdgcn_readlane(cv, 3 * j + 1);
+      if (cur < 0 || hi == cur) continue;
       double sq[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         sq[m] = wave_sum(acc[j][m]);
         acc[j][m] = 0.0;
       }
-      const PieceRec pr = load_piece(A, ((size_t)s * kCovMaxSpl + j) * kMaxKnots, hi[j], npc[j]);
-      if (lane == cur[j]) mo_add(mo + ((size_t)j * kMaxKnots + cur[j]) * 4, sq);
-      if (lane == 0) L.rec[j] = pr;
-      cur[j] = hi[j];
-      xn[j] = pr.xn;
+      if (lane == cur) mo_add(mo + ((size_t)j * kMaxKnots + cur) * 4, sq);
+      load_rec(j, hi, __builtin_amdgcn_readlane(cv, 3 * j + 2));
+      cv = lane == 3 * j ? hi : cv;
     }
-    wave_lds_sync();
   }
   // the last pieces
 #pragma unroll
-  for (int j = 0; j < kCovMaxSpl; ++j) {
+  for (int j = 0; j < NS; ++j) {
     if (j >= n_spl) break;
-    if (cur[j] < 0) continue;
+    const int cur = __builtin_amdgcn_readlane(cv, 3 * j);
+    if (cur < 0) continue;
     double sq[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) sq[m] = wave_sum(acc[j][m]);
-    if (lane == cur[j]) mo_add(mo + ((size_t)j * kMaxKnots + cur[j]) * 4, sq);
+    if (lane == cur) mo_add(mo + ((size_t)j * kMaxKnots + cur) * 4, sq);
   }
   // state results
   const double Ls = wave_sum(lsum);
@@ -360,10 +349,10 @@ __global__ __launch_bounds__(256) void k_cov_grad(CovArgs A, double* __restrict_
     dparams[LPS_P_ATM * (size_t)A.n_states + s] = 2.0 * a_tm * Gwt;
     dparams[LPS_P_U * (size_t)A.n_states + s] = Glin;
     dparams[LPS_P_ALPHA * (size_t)A.n_states + s] = Glinx;
-    if (n_params > 4) dparams[LPS_P_UFG * (size_t)A.n_states + s] = kLn10 * Gfg;
+    if (n_params > 4) dparams[LPS_P_UFG * (size_t)A.n_states + s] = kLn10 * sc.efg * Gfg;
   }
   wave_lds_sync();
-  BackLds& B = *reinterpret_cast<BackLds*>(&L.val[0][0][0]);
+  BackLds& B = *reinterpret_cast<BackLds*>(&L.val[0][0]);
   for (int j = 0; j < n_spl; ++j) {
     int a, n;
     knot_range(off, kcnt, s * n_spl + j, n_knots, a, n);
@@ -397,7 +386,8 @@ lps_status lps_cov_loglike_grad_batch(lps_cov_ctx* c, const lps_states* st, doub
   hipError_t e = launch_cov_coeffs(c, st, s);
   if (e != hipSuccess) return device_status(e);
   const CovArgs A = cov_args(c, st);
-  hipLaunchKernelGGL(k_cov_grad, dim3((n + 3) / 4), dim3(256), 0, s, A, c->gmo, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x,
+  auto kern = c->n_spl <= 4 ? k_cov_grad<4> : (c->n_spl <= 7 ? k_cov_grad<7> : k_cov_grad<kCovMaxSpl>);
+  hipLaunchKernelGGL(kern, dim3((n + 3) / 4), dim3(256), 0, s, A, c->gmo, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x,
                      st->knot_y, c->n_params, c->c0, logL, dparams, dknot_x, dknot_y, status);
   return device_status(hipGetLastError());
 }

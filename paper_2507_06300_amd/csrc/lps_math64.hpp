@@ -16,31 +16,38 @@ namespace lps {
 
 constexpr double kLog2e = 1.442695040888963407359924681001892137426645954153;
 
-// v_fma_f64 with every operand in a register.  (Written out because the
-// compiler otherwise turns a Horner step with a constant addend into a move
-// plus a two-address fmac.)
+// v_fma_f64 with every operand in a register: the addend c (a polynomial
+// coefficient at the call sites) in a vector register, or in a scalar register
+// pair with kSgpr (for kernels whose vector registers are the scarcer kind).
+// (Written out because the compiler otherwise turns a Horner step with a
+// constant addend into a move plus a two-address fmac.)
+template <bool kSgpr = false>
 __device__ inline double fma3(double a, double b, double c) {
   double r;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  if constexpr (kSgpr)
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  else
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
   return r;
 }
 
 // 2^y: y = n + f with n = rint(y), |f| <= 1/2; e^(f ln 2) by the Taylor series
 // to degree 13 (Horner), scaled by 2^n.  Propagates NaN; saturates to 0 / inf.
+template <bool kSgpr = false>
 __device__ inline double exp2_d(double y) {
   const double n = rint(y);
   const double t = (y - n) * kLn2;
   double p = 1.0 / 6227020800.0;          // 1/13!
-  p = fma3(p, t, 1.0 / 479001600.0);      // 1/12!
-  p = fma3(p, t, 1.0 / 39916800.0);
-  p = fma3(p, t, 1.0 / 3628800.0);
-  p = fma3(p, t, 1.0 / 362880.0);
-  p = fma3(p, t, 1.0 / 40320.0);
-  p = fma3(p, t, 1.0 / 5040.0);
-  p = fma3(p, t, 1.0 / 720.0);
-  p = fma3(p, t, 1.0 / 120.0);
-  p = fma3(p, t, 1.0 / 24.0);
-  p = fma3(p, t, 1.0 / 6.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 479001600.0);      // 1/12!
+  p = fma3<kSgpr>(p, t, 1.0 / 39916800.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 3628800.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 362880.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 40320.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 5040.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 720.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 120.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 24.0);
+  p = fma3<kSgpr>(p, t, 1.0 / 6.0);
   p = fma(p, t, 0.5);
   p = fma(p, t, 1.0);
   p = fma(p, t, 1.0);
@@ -77,6 +84,7 @@ __device__ inline double sqrt_d(double x) {
 // s^21 (truncation below 2^-56 relative); e ln 2 with a two-part ln 2 whose
 // leading part has trailing zero bits (exact products for |e| < 2^11).
 // Non-positive or non-finite x gives NaN (the caller flags the bin).
+template <bool kSgpr = false>
 __device__ inline double log_d(double x) {
   int e = __builtin_amdgcn_frexp_exp(x);
   double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
@@ -90,15 +98,15 @@ __device__ inline double log_d(double x) {
   sv = fma(fma(-den, sv, num), r, sv);
   const double z = sv * sv;
   double p = 2.0 / 21.0;
-  p = fma3(p, z, 2.0 / 19.0);
-  p = fma3(p, z, 2.0 / 17.0);
-  p = fma3(p, z, 2.0 / 15.0);
-  p = fma3(p, z, 2.0 / 13.0);
-  p = fma3(p, z, 2.0 / 11.0);
-  p = fma3(p, z, 2.0 / 9.0);
-  p = fma3(p, z, 2.0 / 7.0);
-  p = fma3(p, z, 2.0 / 5.0);
-  p = fma3(p, z, 2.0 / 3.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 19.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 17.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 15.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 13.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 11.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 9.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 7.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 5.0);
+  p = fma3<kSgpr>(p, z, 2.0 / 3.0);
   const double lm = fma(sv * z, p, 2.0 * sv);
   const double fe = (double)e;
   const double res = fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, lm));
