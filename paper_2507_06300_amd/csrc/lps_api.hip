@@ -96,7 +96,7 @@ void free_ctx(lps_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->f,      c->nk,        c->D,       c->R,        c->Rfg,      c->x,       c->sigma,
                   c->tmpl,   c->tab64,     c->tab32,   c->c0,       c->bx,       c->coef64,  c->coef32,
-                  c->n_int,  c->scal,      c->status_ws, c->partial, c->gpartial, c->moments, c->plain_part,
+                  c->n_int,  c->scal,      c->status_ws, c->partial, c->run_sum, c->gpartial, c->moments, c->plain_part,
                   c->sticky, c->wide_list, c->wide_count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -231,6 +231,7 @@ lps_status lps_create(const lps_dataset_desc* d, int device, lps_ctx** out) {
   ok = ok && dalloc(&c->scal, S) == hipSuccess;
   ok = ok && dalloc(&c->status_ws, S) == hipSuccess;
   ok = ok && dalloc(&c->partial, S * nchunk) == hipSuccess;
+  ok = ok && dalloc(&c->run_sum, S * lps::kFinalizeRuns) == hipSuccess;
   ok = ok && dalloc(&c->plain_part, (size_t)c->plain_blocks) == hipSuccess;
   ok = ok && dalloc(&c->sticky, 1) == hipSuccess;
   // queue of single-precision chunk partials to re-evaluate in double range

@@ -19,12 +19,14 @@
 // state whose chunk lies inside one piece of every group (the usual case)
 // runs a straight-line body; a crossing state selects the piece per bin.
 // Lane sums are stored transposed in LDS and one lane per state adds the 64
-// of them in a fixed order, in double, giving one partial per (state, chunk).
-// A second kernel adds the partials of a state in a fixed order and the
-// scaling constant C0:
+// of them in a fixed order, in double, giving one partial per (state, chunk),
+// stored chunk-major so that a tile's partials of one chunk are contiguous.
+// Two small kernels then add the partials of a state in a fixed order (runs
+// of consecutive chunks, then the runs in order) and the scaling constant C0:
 //   logL = C0 - sum_chunks partial.
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lps_batched.hpp"
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int 
                                               const double* __restrict__ coef64, const int32_t* __restrict__ n_int,
                                               const StateScalars* __restrict__ scal,
                                               const uint32_t* __restrict__ wide_count,
-                                              const int2* __restrict__ wide_list, int wide_cap,
+                                              const int2* __restrict__ wide_list, int wide_cap, int n_states,
                                               double* __restrict__ partial) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int 
     const int s = uniform(it.x), chunk = uniform(it.y);
     const double d = wave_sum(lane_terms_wide<MODE, NCH, FG>(s, chunk * chunk_bins, chunk_bins / kWave, lane, K,
                                                              k_pad, tab64, bx, coef64, n_int, scal));
-    if (lane == 0) partial[(size_t)s * n_chunks + chunk] = d;
+    if (lane == 0) partial[(size_t)chunk * n_states + s] = d;
   }
 }
 
@@ -233,6 +235,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);
+    // the lane index, opaque to the compiler here: the LDS addresses below are
+    // formed again per sub-tile instead of being held (and spilled) across the
+    // whole work item
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
     // ---- locate: lane p owns the piece of (state sub + p / G, group p % G) ----
     const int ps = lane / G, pg = lane - (lane / G) * G;
     const bool pv = ps < nsub && ps < SUB;
@@ -276,19 +283,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
       piece_rec(pi0, bx[pbase + pi0], pi1 > pi0 ? xf : xo, r4, off);
       if constexpr (kLocalPoly) {
         // the cubic term d dx^3 over the chunk, |dx| <= h
-        const double h = fmax(xl - xo, xo - xf);
+        const double h = readlane_r(fmax(xl - xo, xo - xf), 0);   // uniform: a scalar register pair
         pquad = fabs(coef64[(pbase + pi0) * 4 + 3]) * h * h * h <= kQuadTol;
       }
-      lcoef[wv][lane] = r4;
-      loff[wv][lane] = off;
+      lcoef[wv][ln] = r4;
+      loff[wv][ln] = off;
       if (pi1 > pi0) {
         // the chunk crosses breakpoint pi0 + 1: stage the next piece as well,
         // with the abscissa (in the table's units) where it takes over
         const double b1 = b_next;
         piece_rec(pi0 + 1, b1, b1, r4, off);
-        lcoef2[wv][lane] = r4;
-        loff2[wv][lane] = off;
-        llim[wv][lane] = kMixed ? (R)(b1 - xo) : (R)b1;
+        lcoef2[wv][ln] = r4;
+        loff2[wv][ln] = off;
+        llim[wv][ln] = kMixed ? (R)(b1 - xo) : (R)b1;
       }
     }
     if constexpr (kScalars) {
@@ -577,7 +584,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
 #pragma unroll
       for (int d = 1; d < LP; ++d) tot += __shfl_down(sum, d, kWave);
       if (mine && r == 0) {
-        partial[(size_t)(sub + q) * n_chunks + chunk] = tot;
+        partial[(size_t)chunk * n_states + (sub + q)] = tot;
         if (kMixed && !isfinite(tot)) {
           // a channel PSD left the single-precision range (a wildly swinging
           // spline): queue the (state, chunk) for the double-range pass
@@ -592,23 +599,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
 }
 
 // logL = C0 - sum over chunks (fixed order), -inf for invalid states.
-__global__ __launch_bounds__(256) void k_finalize(int n_states, int n_chunks, const double* __restrict__ partial,
+// Sum of the partials of chunks [run * run_len, (run + 1) * run_len) of every
+// state, one lane per state (the chunk-major partials make each load of a
+// wave one contiguous row); eight interleaved sums, so that eight loads are in
+// flight, added in a fixed order.
+__global__ __launch_bounds__(kWave) void k_finalize_runs(int n_states, int n_chunks, int run_len,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ run_sum) {
+  const int s = blockIdx.x * kWave + threadIdx.x;
+  const int run = blockIdx.y;
+  if (s >= n_states) return;
+  const int c0 = run * run_len, c1 = min(n_chunks, c0 + run_len);
+  const double* p = partial + s;
+  const size_t n = (size_t)n_states;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = c0;
+  for (; c + 7 < c1; c += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[(c + u) * n];
+  for (; c < c1; ++c) a[0] += p[c * n];
+  run_sum[(size_t)run * n + s] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// logL = C0 - the runs' sums added in run order (all loads issued first); the
+// state's status word.
+__global__ __launch_bounds__(256) void k_finalize(int n_states, int n_runs, const double* __restrict__ run_sum,
                                                   const double* __restrict__ c0,
                                                   const uint32_t* __restrict__ status_ws, double* __restrict__ logL,
                                                   uint32_t* __restrict__ status) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int s = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_states) return;
+  double v[kFinalizeRuns];
+#pragma unroll
+  for (int r = 0; r < kFinalizeRuns; ++r) v[r] = r < n_runs ? run_sum[(size_t)r * n_states + s] : 0.0;
   double acc = 0.0;
-  for (int c = lane; c < n_chunks; c += kWave) acc += partial[(size_t)s * n_chunks + c];
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    uint32_t st = status_ws[s];
-    double v = c0[0] - acc;
-    if (st == 0 && !isfinite(v)) st |= LPS_ST_PSD;
-    logL[s] = st ? -INFINITY : v;
-    if (status) status[s] = st;
-  }
+#pragma unroll
+  for (int r = 0; r < kFinalizeRuns; ++r) acc += v[r];
+  uint32_t st = status_ws[s];
+  const double val = c0[0] - acc;
+  if (st == 0 && !isfinite(val)) st |= LPS_ST_PSD;
+  logL[s] = st ? -INFINITY : val;
+  if (status) status[s] = st;
 }
 
 template <typename R, int B, bool UNI>
@@ -644,13 +675,13 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
   return hipGetLastError();
 }
 
-hipError_t dispatch_wide(lps_ctx* ctx, int n_chunks, int chunk_bins, hipStream_t s) {
+hipError_t dispatch_wide(lps_ctx* ctx, int n_states, int n_chunks, int chunk_bins, hipStream_t s) {
   const Layout& L = ctx->lay;
   const dim3 grid(256), block(kWave * kWavesPerBlock);
 #define LPS_WIDE(MODE, NCH, FG)                                                                               \
   hipLaunchKernelGGL((k_wide<MODE, NCH, FG>), grid, block, 0, s, n_chunks, chunk_bins, ctx->n_bins, ctx->k_pad64, \
                      ctx->tab64, ctx->bx, ctx->coef64, ctx->n_int, ctx->scal, ctx->wide_count, ctx->wide_list,  \
-                     ctx->wide_cap, ctx->partial)
+                     ctx->wide_cap, n_states, ctx->partial)
   const bool fg = L.has_fg != 0;
   if (L.mode == kSplit && L.nch == 2 && !fg) LPS_WIDE(kSplit, 2, false);
   else if (L.mode == kSplit && L.nch == 2 && fg) LPS_WIDE(kSplit, 2, true);
@@ -730,11 +761,17 @@ hipError_t launch_forward(lps_ctx* ctx, const lps_states* st, lps_precision prec
   if (e != hipSuccess) return e;
   timing_end(ctx, s);
   if (mixed) {
-    e = dispatch_wide(ctx, n_chunks, chunk, s);
+    e = dispatch_wide(ctx, n, n_chunks, chunk, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_finalize, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kWave * kWavesPerBlock), 0,
-                     s, n, n_chunks, ctx->partial, ctx->c0, ctx->status_ws, logL, status);
+  // runs of consecutive chunks: their number depends on n_chunks alone, so a
+  // state's sum order does not depend on the batch it is evaluated in
+  const int n_runs = std::min(kFinalizeRuns, n_chunks);
+  const int run_len = (n_chunks + n_runs - 1) / n_runs;
+  hipLaunchKernelGGL(k_finalize_runs, dim3((n + kWave - 1) / kWave, n_runs), dim3(kWave), 0, s, n, n_chunks, run_len,
+                     ctx->partial, ctx->run_sum);
+  hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, n_runs, ctx->run_sum, ctx->c0,
+                     ctx->status_ws, logL, status);
   return hipGetLastError();
 }
 

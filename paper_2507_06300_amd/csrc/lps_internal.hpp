@@ -133,7 +133,8 @@ struct lps_ctx {
   int32_t* n_int;      // [max_states][n_grp] pieces (0 = state invalid)
   lps::StateScalars* scal;   // [max_states]
   uint32_t* status_ws; // [max_states]
-  double* partial;     // [max_states][max(n_chunks64, n_chunks32)]
+  double* partial;     // [max(n_chunks64, n_chunks32)][n_states] (chunk-major)
+  double* run_sum;     // [kFinalizeRuns][n_states] partial sums over runs of chunks
   double* gpartial;    // gradient workspace (see lps_grad.hip)
   size_t gpartial_bytes;
   double* moments;     // [max_grad_states][n_grp][kMaxKnots][4] per-piece adjoint moments
@@ -198,6 +199,10 @@ __host__ __device__ inline double block_origin(const double* x, int kb, int K) {
 }
 
 constexpr int kPlainBlock = 256;
+
+// The batched forward adds a state's chunk partials in this many runs of
+// consecutive chunks (fewer where there are fewer chunks), then adds the runs.
+constexpr int kFinalizeRuns = 64;
 
 // A piece whose cubic term changes its exponent by at most this much (log2
 // units, 4e-8 relative in 2^Q: under one unit in the last place of a single-
