@@ -318,9 +318,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R
   const double xl = x64[klast];
   // abscissa origin of the single-precision table rows (midpoint of their 512-bin block)
   const double xo = kMixed ? block_origin(x64, (kbase / ref_chunk) * ref_chunk, K) : 0.0;
+  // powers of the bins' abscissae about the chunk's first abscissa xf, shared
+  // by every state: the first-piece moments are summed about xf (one add and
+  // three FMAs per group and bin) and moved to the piece start b <= xf by the
+  // finisher; x - xf >= 0 and xf - b >= 0 keep every term of that move of one
+  // sign
+  R P1[B], P2[B], P3[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    P1[b] = kMixed ? xr[b] - (R)(xf - xo) : (R)(xr[b] - xf);
+    P2[b] = P1[b] * P1[b];
+    P3[b] = P2[b] * P1[b];
+  }
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);
+    // the lane index, opaque to the compiler here: the LDS addresses below are
+    // formed again per sub-tile instead of being held (and spilled) across the
+    // whole work item
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
     // ---- locate: lane p owns the piece of (state sub + p / G, group p % G) ----
     const int ps = lane / G, pg = lane - (lane / G) * G;
     const bool pv = ps < nsub;
@@ -355,15 +372,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R
       R4 r4;
       R qo;
       stage(pi0, b0, pi1 > pi0 ? xf : xo, r4, qo);
-      lc0[wv][lane] = r4;
-      lq0[wv][lane] = qo;
-      loff0[wv][lane] = kMixed ? (R)(xo - b0) : (R)(-b0);
+      lc0[wv][ln] = r4;
+      lq0[wv][ln] = qo;
+      loff0[wv][ln] = kMixed ? (R)(xo - b0) : (R)(-b0);
       if (pi1 > pi0) {
         stage(pi0 + 1, b_next, b_next, r4, qo);
-        lc1[wv][lane] = r4;
-        lq1[wv][lane] = qo;
-        loff1[wv][lane] = kMixed ? (R)(xo - b_next) : (R)(-b_next);
-        llim[wv][lane] = kMixed ? (R)(b_next - xo) : (R)b_next;
+        lc1[wv][ln] = r4;
+        lq1[wv][ln] = qo;
+        loff1[wv][ln] = kMixed ? (R)(xo - b_next) : (R)(-b_next);
+        llim[wv][ln] = kMixed ? (R)(b_next - xo) : (R)b_next;
       }
     }
     if constexpr (kScalars) {
@@ -407,9 +424,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R
           const R o0 = loff0[wv][q * G + g];
 #pragma unroll
           for (int b = 0; b < B; ++b) {
-            T[g][b] = xr[b] + o0;
             // single precision: the cubic about the block midpoint (offset 0)
-            const R tq = kMixed ? xr[b] : T[g][b];
+            const R tq = kMixed ? xr[b] : xr[b] + o0;
             Qe[g][b] = c0.x + tq * (c0.y + tq * (c0.z + tq * c0.w));
           }
         }
@@ -516,7 +532,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R
             for (int g = 0; g < G; ++g) gq_keep[g][b] = o.gq[g][b];
         }
       }
-      // moments of the first piece: bins before the next breakpoint
+      // moments of the first piece about the chunk origin: bins before the next breakpoint
       auto accum_moments = [&](auto first_piece_only) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -528,12 +544,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R
           for (int b = 0; b < B; ++b) {
             R gq = gq_keep[g][b];
             if constexpr (decltype(first_piece_only)::value) gq = xr[b] < lim1 ? gq : (R)0;
-            const R tt = T[g][b];
-            const R u1 = gq * tt, u2 = u1 * tt;
             vf[4 + 4 * g + 0] += gq;
-            vf[4 + 4 * g + 1] += u1;
-            vf[4 + 4 * g + 2] += u2;
-            vf[4 + 4 * g + 3] += u2 * tt;
+            vf[4 + 4 * g + 1] = fma(gq, P1[b], vf[4 + 4 * g + 1]);
+            vf[4 + 4 * g + 2] = fma(gq, P2[b], vf[4 + 4 * g + 2]);
+            vf[4 + 4 * g + 3] = fma(gq, P3[b], vf[4 + 4 * g + 3]);
           }
         }
       };
@@ -606,6 +620,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GradWaves<R
   }
 }
 
+// Origin xc of the first-piece moments of chunk c (chunks of `bins` bins):
+// the chunk's first abscissa.
+struct ChunkOrigin {
+  const double* x;
+  int bins;
+  __device__ double at(int c) const { return x[(size_t)c * bins]; }
+};
+
 // Per-wave LDS of the finishing kernel.
 
 // LDS of the finishing kernel: one workgroup per state.
@@ -628,14 +650,16 @@ __device__ inline uint64_t wave_or64(uint64_t v) {
 // collects the last-piece moments of the chunk that straddles into it (if
 // any) followed by the first-piece moments of every chunk that starts in it,
 // in chunk order; pieces lying strictly inside a straddling chunk were
-// written to `moments` by k_grad.  Lanes walk 64 chunks at a time; a
+// written to `moments` by k_grad.  A record's first-piece moments R_k are
+// taken about its chunk's first abscissa xc and moved here to the piece
+// start b (d = xc - b >= 0): M_m = sum_k C(m, k) d^(m - k) R_k.  Lanes walk 64 chunks at a time; a
 // segmented scan keyed by the starting piece sums the chunks of one piece,
 // so the order of every sum is fixed.
 template <typename RT>
-__device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks, int ni,
-                             const RT* __restrict__ rec, const int2* __restrict__ gidx,
-                             const double* __restrict__ glast, const double* __restrict__ moments,
-                             double (*mo)[4]) {
+__device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks, int ni, const ChunkOrigin& org,
+                             const double* __restrict__ bx, const RT* __restrict__ rec,
+                             const int2* __restrict__ gidx, const double* __restrict__ glast,
+                             const double* __restrict__ moments, double (*mo)[4]) {
   for (int p = 0; p < 4; ++p) mo[lane][p] = 0.0;
   uint64_t inner = 0;
   wave_lds_sync();
@@ -647,6 +671,13 @@ __device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks
     double v[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) v[p] = have ? (double)rec[ro * NV + 4 + 4 * g + p] : 0.0;
+    if (have) {
+      const double d = org.at(c) - bx[(size_t)(s * G + g) * kMaxKnots + ab.x];
+      const double m0 = v[0], m1 = v[1], m2 = v[2];
+      v[1] = m1 + d * m0;
+      v[2] = m2 + d * (2.0 * m1 + d * m0);
+      v[3] = v[3] + d * (3.0 * m2 + d * (3.0 * m1 + d * m0));
+    }
     if (ab.y > ab.x) {
       const double* last = glast + (ro * G + g) * 4;
 #pragma unroll
@@ -690,7 +721,7 @@ __device__ void stitch_group(int lane, int s, int g, int G, int NV, int n_chunks
 // gradients and run the spline backward one spline per wave.
 template <typename RT>
 __global__ __launch_bounds__(256) void k_grad_finish(
-    int n_states, int n_spl, int n_params, int NV, int n_chunks, Layout lay, double x_knee,
+    int n_states, int n_spl, int n_params, int NV, int n_chunks, ChunkOrigin org, Layout lay, double x_knee,
     const double* __restrict__ params, const int32_t* __restrict__ off, const int32_t* __restrict__ kcnt, int64_t n_knots,
     const double* __restrict__ kx, const double* __restrict__ ky, const int32_t* __restrict__ n_int,
     const double* __restrict__ bx, const RT* __restrict__ rec, const int2* __restrict__ gidx,
@@ -744,7 +775,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(
     return;
   }
   for (int g = wv; g < G; g += kWavesPerBlock)
-    stitch_group(lane, s, g, G, NV, n_chunks, n_int[s * G + g], rec, gidx, glast, moments, L.mo[g]);
+    stitch_group(lane, s, g, G, NV, n_chunks, n_int[s * G + g], org, bx, rec, gidx, glast, moments, L.mo[g]);
   __syncthreads();
   if (wv == 0) {
     const double a_oms = params[LPS_P_AOMS * (size_t)n_states + s];
@@ -877,7 +908,7 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
     if (e != hipSuccess) return e;
     timing_end(ctx, s);
     hipLaunchKernelGGL(k_grad_finish<float>, fgrid, fblock, 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
-                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y,
+                       ChunkOrigin{ctx->x, chunk}, ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y,
                        ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, lrec, ctx->c0, ctx->status_ws, logL,
                        dparams, dkx, dky, status);
   } else {
@@ -887,7 +918,7 @@ hipError_t launch_grad(lps_ctx* ctx, const lps_states* st, lps_precision prec, d
     if (e != hipSuccess) return e;
     timing_end(ctx, s);
     hipLaunchKernelGGL(k_grad_finish<double>, fgrid, fblock, 0, s, n, ctx->n_spl, ctx->n_params, NV, n_chunks,
-                       ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y,
+                       ChunkOrigin{ctx->x, chunk}, ctx->lay, log10(ctx->f_knee), st->params, st->knot_off, st->knot_cnt, st->n_knots, st->knot_x, st->knot_y,
                        ctx->n_int, ctx->bx, rec, gidx, glast, ctx->moments, nullptr, ctx->c0, ctx->status_ws, logL,
                        dparams, dkx, dky, status);
   }
