@@ -598,7 +598,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
   }   // items
 }
 
-// logL = C0 - sum over chunks (fixed order), -inf for invalid states.
 // Sum of the partials of chunks [run * run_len, (run + 1) * run_len) of every
 // state, one lane per state (the chunk-major partials make each load of a
 // wave one contiguous row); eight interleaved sums, so that eight loads are in
