@@ -139,6 +139,7 @@ struct CovPoint {
   double d[3];    // C_cc (scaled)
   double sn[3];   // Sn_c (scaled)
   double r01, r02, r12;
+  double vs;      // the vine's sqrt((1 - r_AE^2)(1 - r_AT^2))
 };
 
 // The value of slot j at one bin: 10^P, tanh P, or P itself for an unused slot.
@@ -176,7 +177,8 @@ __device__ inline void cov_point_h(const Val& val, const CovRoute& rt, const Sta
   }
   o.r01 = val(rt.gc[0]);
   o.r02 = val(rt.gc[1]);
-  o.r12 = o.r01 * o.r02 + val(rt.gc[2]) * sqrt_d((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
+  o.vs = sqrt_d((1.0 - o.r01 * o.r01) * (1.0 - o.r02 * o.r02));
+  o.r12 = o.r01 * o.r02 + val(rt.gc[2]) * o.vs;
 }
 
 template <typename Val, typename Row>
@@ -191,7 +193,8 @@ struct CovAdj {
   double a00, a11, a22, a01, a02, a12, det, s01, s02, s12;
 };
 
-__device__ inline CovAdj cov_adj(const CovPoint& p) {
+// The same from given s_ab.
+__device__ inline CovAdj cov_adj_s(const CovPoint& p, double s01, double s02, double s12) {
   const double d0 = p.d[0], d1 = p.d[1], d2 = p.d[2];
   const double n0 = p.sn[0], n1 = p.sn[1], n2 = p.sn[2];
   const double q01 = p.r01 * p.r01 * (n0 * n1);
@@ -202,26 +205,39 @@ __device__ inline CovAdj cov_adj(const CovPoint& p) {
   c.a11 = d0 * d2 - q02;
   c.a22 = d0 * d1 - q01;
   c.det = d0 * c.a00 - d1 * q02 - d2 * q01 + 2.0 * (p.r01 * p.r02 * p.r12) * (n0 * n1 * n2);
-  c.s01 = sqrt_d(n0 * n1);
-  c.s02 = sqrt_d(n0 * n2);
-  c.s12 = sqrt_d(n1 * n2);
+  c.s01 = s01;
+  c.s02 = s02;
+  c.s12 = s12;
   c.a01 = c.s01 * (p.r02 * p.r12 * n2 - p.r01 * d2);
   c.a02 = c.s02 * (p.r01 * p.r12 * n1 - p.r02 * d1);
   c.a12 = c.s12 * (p.r01 * p.r02 * n0 - p.r12 * d0);
   return c;
 }
 
-// N_k (tr(C^-1 P) + ln det C) at one bin in scaled units from the cofactors;
+__device__ inline CovAdj cov_adj(const CovPoint& p) {
+  return cov_adj_s(p, sqrt_d(p.sn[0] * p.sn[1]), sqrt_d(p.sn[0] * p.sn[2]), sqrt_d(p.sn[1] * p.sn[2]));
+}
+
+// det C tr(C^-1 P) = sum_ab adj_ab P_ab from the cofactors.
+template <typename Row>
+__device__ inline double cov_trace_num(const CovAdj& c, const Row& row) {
+  return c.a00 * row(kRP + 0) + c.a11 * row(kRP + 1) + c.a22 * row(kRP + 2) +
+         2.0 * (c.a01 * row(kRP + 3) + c.a02 * row(kRP + 4) + c.a12 * row(kRP + 5));
+}
+
+// N_k (tr + ln det C) at one bin in scaled units, given tr = tr(C^-1 P);
 // `bad` is set where C is not positive definite or the term is not finite.
 template <bool kSgpr = false, typename Row>
-__device__ inline double cov_term_adj(const CovAdj& c, const CovPoint& p, const Row& row, bool& bad) {
-  const double num = c.a00 * row(kRP + 0) + c.a11 * row(kRP + 1) + c.a22 * row(kRP + 2) +
-                     2.0 * (c.a01 * row(kRP + 3) + c.a02 * row(kRP + 4) + c.a12 * row(kRP + 5));
-  const double tr = num / c.det;
+__device__ inline double cov_term_tr(const CovAdj& c, const CovPoint& p, const Row& row, double tr, bool& bad) {
   const double ld = log_d<kSgpr>(c.det);
   const bool ok = p.d[0] > 0.0 && c.a22 > 0.0 && c.det > 0.0 && isfinite(tr) && isfinite(ld);
   bad = bad || !ok;
   return row(kRnu) * (tr + ld);
+}
+
+template <bool kSgpr = false, typename Row>
+__device__ inline double cov_term_adj(const CovAdj& c, const CovPoint& p, const Row& row, bool& bad) {
+  return cov_term_tr<kSgpr>(c, p, row, cov_trace_num(c, row) / c.det, bad);
 }
 
 template <typename Row>

@@ -196,10 +196,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const double hf = background_factor<true>(A.rt, sc, x, A.x_knee);
       CovPoint p;
       cov_point_h(val, A.rt, sc, hf, rw, p);
-      const CovAdj cj = cov_adj(p);
-      lsum += cov_term_adj<true>(cj, p, rw, bad);
-      const double nu = rw(kRnu);
+      // sqrt(Sn_a Sn_b) = sqrt(Sn_a) sqrt(Sn_b) and the 1 / Sn_c below from
+      // three reciprocal square roots (0 where Sn_c = 0, as sqrt gives)
+      double ir[3], qs[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ir[c] = p.sn[c] > 0.0 ? rsq_d(p.sn[c]) : 0.0;
+        qs[c] = p.sn[c] * ir[c];
+      }
+      const CovAdj cj = cov_adj_s(p, qs[0] * qs[1], qs[0] * qs[2], qs[1] * qs[2]);
       const double id = rcp_d(cj.det);
+      lsum += cov_term_tr<true>(cj, p, rw, cov_trace_num(cj, rw) * id, bad);
+      const double nu = rw(kRnu);
       const double ci00 = cj.a00 * id, ci11 = cj.a11 * id, ci22 = cj.a22 * id;
       const double ci01 = cj.a01 * id, ci02 = cj.a02 * id, ci12 = cj.a12 * id;
       const double P00 = rw(kRP + 0), P11 = rw(kRP + 1), P22 = rw(kRP + 2);
@@ -225,13 +233,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const double gC01 = -2.0 * nu * G01, gC02 = -2.0 * nu * G02, gC12 = -2.0 * nu * G12;
       const double c01 = p.r01 * cj.s01, c02 = p.r02 * cj.s02, c12 = p.r12 * cj.s12;
       const double gsh[3] = {gC00, gC11, gC22};
-      const double gsn[3] = {gC00 + (gC01 * c01 + gC02 * c02) * (0.5 * rcp_d(p.sn[0])),
-                             gC11 + (gC01 * c01 + gC12 * c12) * (0.5 * rcp_d(p.sn[1])),
-                             gC22 + (gC02 * c02 + gC12 * c12) * (0.5 * rcp_d(p.sn[2]))};
+      const double gsn[3] = {gC00 + (gC01 * c01 + gC02 * c02) * (0.5 * ir[0] * ir[0]),
+                             gC11 + (gC01 * c01 + gC12 * c12) * (0.5 * ir[1] * ir[1]),
+                             gC22 + (gC02 * c02 + gC12 * c12) * (0.5 * ir[2] * ir[2])};
       double gr01 = gC01 * cj.s01, gr02 = gC02 * cj.s02;
       const double gr12 = gC12 * cj.s12;
       const double pp = val(A.rt.gc[2]);
-      const double S = sqrt_d((1.0 - p.r01 * p.r01) * (1.0 - p.r02 * p.r02));
+      const double S = p.vs;
       // S = 0 only where a correlation is exactly +-1; S is then 0 whatever the
       // other correlation, so its derivative terms drop out
       const double iS = S > 0.0 ? rcp_d(S) : 0.0;

@@ -79,6 +79,15 @@ __device__ inline double sqrt_d(double x) {
   return x > 0.0 ? g : (x == 0.0 ? 0.0 : NAN);
 }
 
+// 1/sqrt x for a positive normal x: hardware estimate and two Newton steps
+// y <- y + y (1 - x y^2) / 2 (within an ulp or two).
+__device__ inline double rsq_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // ln x for a positive normal x: x = m 2^e with m in [1/sqrt2, sqrt2),
 // ln m = 2 atanh s, s = (m - 1)/(m + 1), |s| < 0.172, by its odd series to
 // s^21 (truncation below 2^-56 relative); e ln 2 with a two-part ln 2 whose
