@@ -138,10 +138,13 @@ __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int 
 
 // Waves per SIMD the register allocation must allow: four for the
 // single-precision split layout with merged A/E rows, no foreground and eight
-// bins per lane (the one-year workload's kernel: 128 registers and 40 bytes
+// bins per lane (the one-year workload's kernel: 128 registers and a few bytes
 // spilled outside the bin loop, 5-7 % faster than three waves at 141
 // registers); the other instantiations would spill inside their bin loops at
-// four (the paper layout ran 6x slower) and keep the compiler's choice.
+// four (the paper layout ran 6x slower) and keep the compiler's choice.  (The
+// FP64 kernel of the same layout at four bins per lane, capped at three waves,
+// ran about 1 % faster but spilled 68 bytes per lane, written once per wave:
+// 0.66 GB more HBM writes per launch.)
 template <typename R, int MODE, int NCH, bool FG, int B>
 struct FwdWaves {
   static constexpr int v = (sizeof(R) == 4 && MODE == kSplit && NCH == 2 && !FG && B == 8) ? 4 : 1;
@@ -181,7 +184,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
   __shared__ R loff[kWavesPerBlock][kWave];
   __shared__ R4 lcoef2[kWavesPerBlock][kWave];   // next piece of a chunk that crosses one breakpoint
   __shared__ R loff2[kWavesPerBlock][kWave];
-  __shared__ R llim[kWavesPerBlock][kWave];
   __shared__ R lscal[kWavesPerBlock][SUB][4];
   __shared__ Acc red[kWavesPerBlock][kWave * SUB];
   const int lane = threadIdx.x & (kWave - 1);
@@ -289,13 +291,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
       lcoef[wv][ln] = r4;
       loff[wv][ln] = off;
       if (pi1 > pi0) {
-        // the chunk crosses breakpoint pi0 + 1: stage the next piece as well,
-        // with the abscissa (in the table's units) where it takes over
+        // the chunk crosses breakpoint pi0 + 1: stage the next piece as well;
+        // its offset is minus the abscissa (in the table's units) where it
+        // takes over, (R)(xo - b1) in single precision and -b1 in FP64
         const double b1 = b_next;
         piece_rec(pi0 + 1, b1, b1, r4, off);
         lcoef2[wv][ln] = r4;
         loff2[wv][ln] = off;
-        llim[wv][ln] = kMixed ? (R)(b1 - xo) : (R)b1;
       }
     }
     if constexpr (kScalars) {
@@ -432,9 +434,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
           } else {     // at most one breakpoint: both staged pieces from LDS, select per bin
             const R4 c0 = lcoef[wv][pl];
             const R4 c1 = lcoef2[wv][pl];
-            const R lim = str ? llim[wv][pl] : (R)INFINITY;
-            const R o0 = loff[wv][pl];
-            const R o1 = str ? loff2[wv][pl] : o0;
+            const R o0 = loff[wv][pl], o2 = loff2[wv][pl];
+            const R lim = str ? -o2 : (R)INFINITY;
+            const R o1 = str ? o2 : o0;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
               const bool second = xr[b] >= lim;
