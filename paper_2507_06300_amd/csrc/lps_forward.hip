@@ -186,6 +186,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
   __shared__ R loff2[kWavesPerBlock][kWave];
   __shared__ R lscal[kWavesPerBlock][SUB][4];
   __shared__ Acc red[kWavesPerBlock][kWave * SUB];
+  // FP64: the table of 2^(j/64) for exp2_t
+  __shared__ double lexp2[kMixed ? 1 : kExp2Tab];
+  if constexpr (!kMixed) {
+    fill_exp2_table(lexp2, (int)threadIdx.x);
+    __syncthreads();
+  }
+  // 2^q: the hardware instruction in single precision, the table in FP64
+  auto ex2 = [&](R q) -> R {
+    if constexpr (kMixed) return Math<R>::exp2_(q);
+    else return exp2_t(q, lexp2);
+  };
   const int lane = threadIdx.x & (kWave - 1);
   // wave-uniform work-item index: keeps all per-state addressing scalar
   const int wv = uniform(threadIdx.x >> 6);
@@ -346,13 +357,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
         const R4 c0 = lcoef[wv][pl];
         if constexpr (kLocalPoly) {
 #pragma unroll
-          for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(c0.x + xr[b] * (c0.y + xr[b] * (c0.z + xr[b] * c0.w)));
+          for (int b = 0; b < B; ++b) E[b] = ex2(c0.x + xr[b] * (c0.y + xr[b] * (c0.z + xr[b] * c0.w)));
         } else {
           const R off = loff[wv][pl];
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             const R tt = xr[b] + off;
-            E[b] = Math<R>::exp2_(c0.x + tt * (c0.y + tt * (c0.z + tt * c0.w)));
+            E[b] = ex2(c0.x + tt * (c0.y + tt * (c0.z + tt * c0.w)));
           }
         }
       };
@@ -391,7 +402,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
             const R4 c0 = lcoef[wv][q * G + g];
             R E[B];
 #pragma unroll
-            for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(c0.x + xr[b] * (c0.y + xr[b] * c0.z));
+            for (int b = 0; b < B; ++b) E[b] = ex2(c0.x + xr[b] * (c0.y + xr[b] * c0.z));
             fold(g, E);
           }
         } else {
@@ -447,7 +458,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
           }
           R E[B];
 #pragma unroll
-          for (int b = 0; b < B; ++b) E[b] = Math<R>::exp2_(Q[b]);
+          for (int b = 0; b < B; ++b) E[b] = ex2(Q[b]);
           fold(g, E);
         }
       }
