@@ -505,9 +505,11 @@ lps_status lps_valu_probe(int device, double* fma_ns_per_wave_instr, double* tra
 
 /*
  * Diagnostic (not part of the hot path): applies one of the double-precision
- * elementary functions of the batched FP64 kernels to x[0..n): fn = 0 exp2,
- * 1 log2, 2 reciprocal, 3 square root, 4 natural logarithm; out[i] receives
- * the result.  Device pointers, asynchronous on `stream`, no allocation.
+ * elementary functions of the batched FP64 kernels to x[0..n): fn = 0 exp2
+ * (series), 1 log2, 2 reciprocal, 3 square root, 4 natural logarithm, 5 exp2
+ * from the 64-entry table of 2^(j/64) (the FP64 forward kernel's), 6
+ * reciprocal square root; out[i] receives the result.  Device pointers,
+ * asynchronous on `stream`, no allocation; LPS_E_SHAPE for fn outside 0..6.
  */
 lps_status lps_math64_check(const double* x, int32_t n, int32_t fn, double* out, void* stream);
 

@@ -488,7 +488,7 @@ class CovContext:
         return C, status
 
 
-MATH64 = {"exp2": 0, "log2": 1, "rcp": 2, "sqrt": 3, "log": 4}
+MATH64 = {"exp2": 0, "log2": 1, "rcp": 2, "sqrt": 3, "log": 4, "exp2_table": 5, "rsq": 6}
 
 
 def math64_check(fn: str, x, stream=None):

@@ -52,6 +52,9 @@ __global__ __launch_bounds__(256) void k_trans_chain(int iters, float seed, floa
 }
 
 __global__ void k_math64(int n, int fn, const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double tab[kExp2Tab];   // for exp2_t, filled before any thread leaves
+  fill_exp2_table(tab, (int)threadIdx.x);
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double v = x[i];
@@ -61,7 +64,9 @@ __global__ void k_math64(int n, int fn, const double* __restrict__ x, double* __
     case 1: r = log2_d(v); break;
     case 2: r = rcp_d(v); break;
     case 3: r = sqrt_d(v); break;
-    default: r = log_d(v); break;
+    case 4: r = log_d(v); break;
+    case 5: r = exp2_t(v, tab); break;
+    default: r = rsq_d(v); break;
   }
   out[i] = r;
 }
@@ -73,7 +78,7 @@ extern "C" lps_status lps_math64_check(const double* x, int32_t n, int32_t fn, d
   LPS_API_RANGE();
   if (n == 0) return LPS_OK;
   if (!x || !out) return LPS_E_NULL;
-  if (n < 0 || fn < 0 || fn > 4) return LPS_E_SHAPE;
+  if (n < 0 || fn < 0 || fn > 6) return LPS_E_SHAPE;
   hipLaunchKernelGGL(lps::k_math64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, fn, x,
                      out);
   return lps::device_status(hipGetLastError());

@@ -1,6 +1,7 @@
 """The double-precision elementary functions of the batched FP64 kernels
-(exp2, log2, reciprocal, square root, natural logarithm), each written out from
-a hardware estimate, Newton steps or a truncated series, against the host C
+(exp2 by its series and from the table of 2^(j/64), log2, reciprocal, square
+root, reciprocal square root, natural logarithm), each written out from a
+hardware estimate, Newton steps or a truncated series, against the host C
 library in units in the last place over the whole range the kernels see."""
 import numpy as np
 import pytest
@@ -24,20 +25,24 @@ def _ulps(got, want):
     return np.abs(got - want) / np.spacing(np.abs(want))
 
 
-def test_exp2(lps):
+@pytest.mark.parametrize("fn", ["exp2", "exp2_table"])
+def test_exp2(lps, fn):
     rng = np.random.default_rng(1)
-    x = np.concatenate([rng.uniform(-1000.0, 1000.0, 100000), rng.uniform(-1.0, 1.0, 100000),
-                        np.arange(-60, 61, dtype=np.float64), [0.0, 0.5, -0.5]])
-    got = lps.math64_check("exp2", x).cpu().numpy()
+    # uniform spreads, the table's nodes j/64 and the midpoints between them
+    # (|r| = 1/128, the series' worst case)
+    nodes = np.arange(-640, 641, dtype=np.float64) / 64.0
+    x = np.concatenate([rng.uniform(-1000.0, 1000.0, 100000), rng.uniform(-1.0, 1.0, 100000), nodes,
+                        nodes + 1.0 / 128.0, np.arange(-60, 61, dtype=np.float64), [0.0, 0.5, -0.5]])
+    got = lps.math64_check(fn, x).cpu().numpy()
     want = np.exp2(x)
-    assert np.max(_ulps(got, want)) <= ULP
+    assert np.max(_ulps(got, want)) <= ULP, (fn, np.max(_ulps(got, want)))
     assert np.all(got[-124:-3] == want[-124:-3])   # integer powers of two are exact
-    edge = lps.math64_check("exp2", np.array([1100.0, -1100.0, np.nan])).cpu().numpy()
+    edge = lps.math64_check(fn, np.array([1100.0, -1100.0, np.nan])).cpu().numpy()
     assert edge[0] == np.inf and edge[1] == 0.0 and np.isnan(edge[2])
 
 
 @pytest.mark.parametrize("fn,ref", [("log2", np.log2), ("log", np.log), ("rcp", lambda v: 1.0 / v),
-                                    ("sqrt", np.sqrt)])
+                                    ("sqrt", np.sqrt), ("rsq", lambda v: 1.0 / np.sqrt(v))])
 def test_positive_argument_functions(lps, fn, ref):
     rng = np.random.default_rng(2)
     x = np.concatenate([10.0 ** rng.uniform(-300.0, 300.0, 100000), rng.uniform(0.5, 2.0, 100000),
