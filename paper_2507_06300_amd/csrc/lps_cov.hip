@@ -26,8 +26,8 @@
 // tr(C^-1 P) = sum_ab adj_ab P_ab / det C.  Positive definiteness is
 // Sylvester's criterion (C_AA > 0, C_AA C_EE - r_AE^2 Sn_A Sn_E > 0,
 // det C > 0).  Powers of ten and tanh use exp2 by range reduction to
-// [-1/2, 1/2] and the Taylor series of e^t to degree 13 (truncation below
-// 2^-55 relative), scaled by ldexp.
+// [-1/2, 1/2] and a degree-11 near-minimax polynomial for e^t (within 0.15
+// ulp before rounding), scaled by ldexp.
 //
 // Work decomposition: the coefficient kernel validates every state and
 // stores the cubic pieces of its splines (one wave per state, one lane per

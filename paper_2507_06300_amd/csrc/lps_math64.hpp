@@ -1,11 +1,11 @@
 // Double-precision elementary functions of the batched kernels, written out
 // from their textbook constructions: a hardware estimate (v_rcp_f64,
-// v_rsq_f64) refined by Newton steps, range reduction plus a truncated Taylor
-// or atanh series.  Each stays within a few ulp of the host C library over
-// the arguments the kernels produce (positive normal numbers for the
-// reciprocal, square root and logarithms; lps_math64_check exposes them for
-// that test), at a fraction of the cost of the library versions, which carry
-// double-double steps.
+// v_rsq_f64) refined by Newton steps, range reduction plus a polynomial
+// (near-minimax, Taylor or atanh series).  Each stays within a few ulp of the
+// host C library over the arguments the kernels produce (positive normal
+// numbers for the reciprocal, square root and logarithms; lps_math64_check
+// exposes them for that test), at a fraction of the cost of the library
+// versions, which carry double-double steps.
 #pragma once
 
 #include <math.h>
@@ -31,24 +31,26 @@ __device__ inline double fma3(double a, double b, double c) {
   return r;
 }
 
-// 2^y: y = n + f with n = rint(y), |f| <= 1/2; e^(f ln 2) by the Taylor series
-// to degree 13 (Horner), scaled by 2^n.  Propagates NaN; saturates to 0 / inf.
+// 2^y: y = n + f with n = rint(y), |f| <= 1/2; e^t, t = f ln 2, by the degree-11
+// polynomial that interpolates e^t at the 12 Chebyshev nodes of [-ln 2 / 2,
+// ln 2 / 2] (coefficients from gen_exp2_poly.py, beside the build script:
+// within 0.15 ulp of e^t before the Horner roundings; two FMAs fewer than the
+// Taylor series to degree 13), scaled by 2^n.  Propagates NaN; saturates to
+// 0 / inf.
 template <bool kSgpr = false>
 __device__ inline double exp2_d(double y) {
   const double n = rint(y);
   const double t = (y - n) * kLn2;
-  double p = 1.0 / 6227020800.0;          // 1/13!
-  p = fma3<kSgpr>(p, t, 1.0 / 479001600.0);      // 1/12!
-  p = fma3<kSgpr>(p, t, 1.0 / 39916800.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 3628800.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 362880.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 40320.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 5040.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 720.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 120.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 24.0);
-  p = fma3<kSgpr>(p, t, 1.0 / 6.0);
-  p = fma(p, t, 0.5);
+  double p = 0x1.af631d0059becp-26;
+  p = fma3<kSgpr>(p, t, 0x1.28b4057f44145p-22);
+  p = fma3<kSgpr>(p, t, 0x1.71ddf5749d126p-19);
+  p = fma3<kSgpr>(p, t, 0x1.a01991ac8730ap-16);
+  p = fma3<kSgpr>(p, t, 0x1.a01a01b14378fp-13);
+  p = fma3<kSgpr>(p, t, 0x1.6c16c187fbe02p-10);
+  p = fma3<kSgpr>(p, t, 0x1.111111110f225p-7);
+  p = fma3<kSgpr>(p, t, 0x1.555555554f0cfp-5);
+  p = fma3<kSgpr>(p, t, 0x1.555555555555ap-3);
+  p = fma3<kSgpr>(p, t, 0x1.0000000000011p-1);
   p = fma(p, t, 1.0);
   p = fma(p, t, 1.0);
   const int e = (int)fmax(fmin(n, 2100.0), -2100.0);
