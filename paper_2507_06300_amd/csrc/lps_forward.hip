@@ -138,8 +138,8 @@ __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int 
 
 // Waves per SIMD the register allocation must allow: four for the
 // single-precision split layout with merged A/E rows, no foreground and eight
-// bins per lane (the one-year workload's kernel: 128 registers and a few bytes
-// spilled outside the bin loop, 5-7 % faster than three waves at 141
+// bins per lane (the one-year workload's kernel: 128 registers and no
+// spills, 5-7 % faster than three waves at 141
 // registers); the other instantiations would spill inside their bin loops at
 // four (the paper layout ran 6x slower) and keep the compiler's choice.  (The
 // FP64 kernel of the same layout at four bins per lane, capped at three waves,
@@ -245,6 +245,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
   const double xl = x64[klast];
   // abscissa origin of the single-precision table rows (midpoint of their block)
   const double xo = kMixed ? block_origin(x64, (kbase / ref_chunk) * ref_chunk, K) : 0.0;
+  // the chunk's half-span about xo (a cubic term d dx^3 over the chunk has
+  // |dx| <= h3r), uniform: a scalar register pair for the whole work item
+  const double h3r = readlane_r(fmax(xl - xo, xo - xf), 0);
 
   for (int sub = s_begin; sub < s_end; sub += SUB) {
     const int nsub = min(SUB, s_end - sub);
@@ -295,9 +298,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FwdWaves<R,
       // chunk start and the next one about its own start
       piece_rec(pi0, bx[pbase + pi0], pi1 > pi0 ? xf : xo, r4, off);
       if constexpr (kLocalPoly) {
-        // the cubic term d dx^3 over the chunk, |dx| <= h
-        const double h = readlane_r(fmax(xl - xo, xo - xf), 0);   // uniform: a scalar register pair
-        pquad = fabs(coef64[(pbase + pi0) * 4 + 3]) * h * h * h <= kQuadTol;
+        // the cubic term d dx^3 over the chunk
+        pquad = fabs(coef64[(pbase + pi0) * 4 + 3]) * h3r * h3r * h3r <= kQuadTol;
       }
       lcoef[wv][ln] = r4;
       loff[wv][ln] = off;
