@@ -113,7 +113,8 @@ __device__ double lane_terms_wide(int s, int kbase, int nb, int lane, int K, int
 }
 
 // The double-range pass of the mixed path: one wave per queued (state, chunk),
-// a fixed grid striding over the queue (empty in the usual case).  The chunk's
+// a fixed grid of eight workgroups per CU striding over the queue (empty in
+// the usual case).  The chunk's
 // partial is replaced by the fixed-order wave sum of its bins' terms.
 template <int MODE, int NCH, bool FG>
 __global__ __launch_bounds__(256) void k_wide(int n_chunks, int chunk_bins, int K, int k_pad,
@@ -691,7 +692,12 @@ hipError_t dispatch(lps_ctx* ctx, int n, int n_chunks, int n_tiles, int tile, co
 
 hipError_t dispatch_wide(lps_ctx* ctx, int n_states, int n_chunks, int chunk_bins, hipStream_t s) {
   const Layout& L = ctx->lay;
-  const dim3 grid(256), block(kWave * kWavesPerBlock);
+  // eight workgroups per CU: a queued chunk is a chain of dependent loads (the
+  // piece search, then the pieces and table rows), so the pass needs many
+  // waves in flight once the queue is long (measured on the one-year grid in
+  // the paper's layout, 0.23 -> 0.09 ms beside the main kernel against one
+  // workgroup per CU); with an empty queue every wave exits after one load
+  const dim3 grid(ctx->n_cu > 0 ? ctx->n_cu * 8 : 2048), block(kWave * kWavesPerBlock);
 #define LPS_WIDE(MODE, NCH, FG)                                                                               \
   hipLaunchKernelGGL((k_wide<MODE, NCH, FG>), grid, block, 0, s, n_chunks, chunk_bins, ctx->n_bins, ctx->k_pad64, \
                      ctx->tab64, ctx->bx, ctx->coef64, ctx->n_int, ctx->scal, ctx->wide_count, ctx->wide_list,  \
